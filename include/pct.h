@@ -1,0 +1,173 @@
+/*
+ * pct.h -- C ABI of the MI355X proton-CT data simulator hot path.
+ *
+ * The library produces the three parts of the linear system A x = b that the
+ * simulator of Witt et al. (arXiv 2108.12369, Sec. II) writes for reconstruction:
+ *   x  the true relative stopping power (RSP) of every voxel of a phantom (Sec. II-A),
+ *   A  one sparse row per proton holding the length of its path in every voxel it
+ *      crosses, in CSR form (Sec. II-C),
+ *   b  the water-equivalent path length of every proton, the inner product of its row
+ *      with x, optionally with noise (Sec. II-C).
+ *
+ * Conventions for every entry point:
+ *   - units are mm, projection angles in degrees, scattering widths in radians;
+ *   - pointers named *_dev are device memory owned by the caller; every other pointer is
+ *     host memory owned by the caller and only read during the call;
+ *   - `stream` is a hipStream_t (NULL: the default stream); every call only enqueues
+ *     work on it, never synchronises it (except pct_device_status) and never allocates
+ *     device memory;
+ *   - descriptors are validated on the host before anything is enqueued; on failure
+ *     nothing is written and the status says why;
+ *   - calls on different streams with disjoint workspaces and outputs may overlap.
+ */
+#ifndef PCT_H
+#define PCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+typedef int32_t pct_status;
+#define PCT_OK          0
+#define PCT_EINVAL     (-1)  /* a descriptor field is out of its documented range      */
+#define PCT_ERANGE     (-2)  /* a size overflows the index types (>= 2^31 voxels)       */
+#define PCT_ECAPACITY  (-3)  /* (device) a row did not fit in nnz_capacity: not stored  */
+#define PCT_EWORKSPACE (-4)  /* workspace missing or smaller than pct_workspace_bytes   */
+#define PCT_EHIP       (-5)  /* a HIP runtime call failed                               */
+#define PCT_EINTERNAL  (-6)  /* (device) emitted entries differ from the counted ones   */
+
+/* ------------------------------------------------------------------ enumerations */
+#define PCT_ELLIPSE    0   /* ellipse in the x-y plane; in 3D an elliptic cylinder along z */
+#define PCT_ELLIPSOID  1   /* ellipsoid (3D); in 2D the same as PCT_ELLIPSE                 */
+
+#define PCT_CORNER_AVG 0   /* pixel value = mean RSP at its 4 (8) corners (Sec. II-A)       */
+#define PCT_CENTER     1   /* pixel value = RSP at its center point (Sec. II-A)             */
+
+#define PCT_STRAIGHT   0   /* straight-line proton paths (Sec. II-B)                        */
+#define PCT_HERMITE    1   /* cubic spline between entry and exit, straight outside (II-B)  */
+
+#define PCT_F32        0   /* stored lengths: binary32                                      */
+#define PCT_F16        1   /* stored lengths: binary16, round to nearest even               */
+
+#define PCT_MIXED      0   /* FP64 geometry and traversal order, FP32 lengths, FP64 WEPL sum */
+#define PCT_PLAIN_F32  1   /* FP32 everywhere (comparison form)                              */
+
+#define PCT_MAX_REGIONS 16
+
+/* One region of a non-homogeneous ellipse object (Sec. II-A).  A point belongs to the
+ * region when sum(((p - center) / semi)^2) <= 1 over x, y (and z for an ellipsoid in
+ * 3D).  Regions are painted in array order: a later region replaces the RSP of an
+ * earlier one.  Region 0 is the outer boundary used for the proton entry and exit. */
+typedef struct {
+    int32_t shape;      /* PCT_ELLIPSE | PCT_ELLIPSOID */
+    float rsp;          /* relative stopping power, >= 0 */
+    double center[3];   /* mm */
+    double semi[3];     /* semi-axes, mm, > 0 (z ignored unless ellipsoid in 3D) */
+} pct_region;
+
+/* Voxel grid and phantom (Sec. II-A).  Voxel (ix, iy, iz) covers
+ * [origin + i*h, origin + (i+1)*h) per axis and is column ix + n[0]*(iy + n[1]*iz) of A
+ * and element of x.  In 2D n[2] and h[2] are ignored. */
+typedef struct {
+    int32_t dim;                 /* 2 or 3 */
+    int32_t n[3];                /* voxels per axis, >= 1; product < 2^31 */
+    double h[3];                 /* voxel size, mm, > 0 */
+    double origin[3];            /* lower corner of the grid box, mm */
+    int32_t n_regions;           /* 1..PCT_MAX_REGIONS */
+    int32_t voxelize;            /* PCT_CORNER_AVG | PCT_CENTER */
+    const pct_region *regions;   /* host array of n_regions */
+} pct_phantom;
+
+/* Parallel beam and proton source (Sec. II-B).  Proton g (0 <= g < n_protons) belongs
+ * to projection angle k with floor(k P/K) <= g < floor((k+1) P/K), i.e. angle-major
+ * order, angle k at angle0_deg + k*dangle_deg.  Its entry offset is uniform on
+ * [t_range) along t (and [v_range) along v in 3D).  Every random number of proton g is
+ * drawn from Philox4x32-10 keyed by `seed` with a counter built from g, so any row can
+ * be produced alone.  A call covers the rows [row_begin, row_begin + row_count). */
+typedef struct {
+    uint64_t seed;
+    int32_t n_angles;            /* K >= 1 */
+    int32_t path;                /* PCT_STRAIGHT | PCT_HERMITE */
+    double angle0_deg;
+    double dangle_deg;
+    int64_t n_protons;           /* P >= 0 */
+    int64_t row_begin;           /* 0 <= row_begin, row_begin + row_count <= P */
+    int64_t row_count;
+    double t_range[2];           /* mm, t_range[0] <= t_range[1] */
+    double v_range[2];           /* mm (3D) */
+    double sigma_in_rad;         /* entry angular spread per plane, 0..0.1 */
+    double sigma_out_rad;        /* exit angular spread per plane, 0..0.1 */
+    double sigma_lat_mm;         /* exit lateral displacement per plane, >= 0 */
+    double rho;                  /* correlation of (lateral, angle) at exit, |rho| <= 1 */
+    double step_mm;              /* spline sample spacing, > 0 (Hermite only); at most
+                                    2^22 samples per outer-boundary diameter x 6, else
+                                    PCT_ERANGE */
+    double noise_rel;            /* relative WEPL noise sigma, >= 0 (0: noiseless) */
+} pct_beam;
+
+/* One simulation job: one phantom, one beam, one range of rows. */
+typedef struct {
+    const pct_phantom *phantom;  /* host */
+    const pct_beam *beam;        /* host */
+    const float *x_dev;          /* true RSP vector from pct_phantom_build (for b) */
+    int64_t *row_ptr_dev;        /* row_count + 1 entries, row_ptr[0] = 0 (job-relative) */
+    int32_t *cols_dev;           /* nnz_capacity entries */
+    void *vals_dev;              /* nnz_capacity entries of val_dtype */
+    int64_t nnz_capacity;        /* >= 0 */
+    float *b_dev;                /* row_count entries; may be NULL in pct_emit_csr */
+    int32_t val_dtype;           /* PCT_F32 | PCT_F16 */
+    int32_t precision;           /* PCT_MIXED | PCT_PLAIN_F32; equal for all jobs of a call */
+} pct_job;
+
+/* Human-readable name of a status code (static string). */
+const char *pct_status_string(pct_status status);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t pct_version(void);
+
+/* Voxelise the phantom into x_dev (n[0]*n[1]*(dim==3 ? n[2] : 1) floats) with the
+ * pixel-value rule of Sec. II-A: the RSP at the voxel center, or the mean of the RSP at
+ * its 4 (2D) or 8 (3D) corners; the point tests are done in binary64 and the value is
+ * rounded once to binary32. */
+pct_status pct_phantom_build(const pct_phantom *phantom, float *x_dev, void *stream);
+
+/* Bytes of device workspace that pct_count_rows / pct_emit_csr / pct_wepl need for
+ * these jobs (0 if a descriptor is invalid).  The workspace holds the job table, the
+ * per-row counts, the scan partials and a status word; its contents between calls
+ * carry the status word only. */
+size_t pct_workspace_bytes(int32_t n_jobs, const pct_job *jobs);
+
+/* Count pass: for every row of every job the number of CSR entries the path produces
+ * (Sec. II-C), then an exclusive scan into row_ptr_dev of each job, and
+ * nnz_total_dev[j] = row_ptr_j[row_count_j] (device int64 array of n_jobs).  Clears the
+ * device status word.  The caller reads nnz_total to size cols / vals. */
+pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_t ws_bytes,
+                          int64_t *nnz_total_dev, void *stream);
+
+/* Emit pass: traverse every path again and write its entries at
+ * [row_ptr[r], row_ptr[r+1]) of cols_dev (voxel column) and vals_dev (path length in
+ * that voxel, mm), in path order from entry to exit, and, if b_dev is not NULL, its
+ * WEPL b[r] = sum of length * x[col] (with noise when noise_rel > 0).  row_ptr_dev must
+ * hold the result of pct_count_rows for the same jobs.  A row that would end beyond
+ * nnz_capacity is not written and sets PCT_ECAPACITY in the device status word. */
+pct_status pct_emit_csr(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_t ws_bytes,
+                        void *stream);
+
+/* WEPL only: b_dev[r] for every row, bit-identical to the b that pct_emit_csr writes,
+ * without storing A (row_ptr, cols, vals are not read or written). */
+pct_status pct_wepl(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_t ws_bytes,
+                    void *stream);
+
+/* Synchronise the stream and return the device status word of the workspace:
+ * PCT_OK, PCT_ECAPACITY or PCT_EINTERNAL (first error since the last count pass). */
+pct_status pct_device_status(const void *ws_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCT_H */

@@ -1,0 +1,570 @@
+// pct.hip -- kernels and C ABI of the proton-CT hot path (see include/pct.h).
+//
+// Pipeline of one batch of jobs (one stream, no host synchronisation):
+//   pct_phantom_build : k_phantom          one thread per voxel -> x (FP32)
+//   pct_count_rows    : k_put_jobs          job table into the workspace (kernel args)
+//                       k_count             one lane per row -> per-row entry counts,
+//                                           per-tile sums
+//                       k_scan_tiles        exclusive scan of the tile sums, job totals
+//                       k_row_ptr           per-tile scan of the counts -> row_ptr
+//   pct_emit_csr      : k_put_jobs, k_emit  one lane per row -> cols, vals, b
+//   pct_wepl          : k_put_jobs, k_emit  (no A stores) -> b
+#include "../../include/pct.h"
+#include "pct_device.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+namespace pct {
+
+constexpr int TILE = 256;            // rows per tile (= threads per block of k_count/k_emit)
+constexpr int SCAN_THREADS = 1024;
+
+// Workspace layout (bytes): [0,256) header | job table | tile sums | tile offsets | counts
+struct WsHeader {
+    int32_t status;
+    int32_t pad[63];
+};
+
+static inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t jobs_off, sums_off, offs_off, counts_off, total;
+    int64_t total_tiles, total_rows;
+};
+
+static Layout layout_of(int32_t n_jobs, const int64_t *row_counts) {
+    Layout L{};
+    int64_t tiles = 0, rows = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        tiles += (row_counts[j] + TILE - 1) / TILE;
+        rows += row_counts[j];
+    }
+    L.total_tiles = tiles;
+    L.total_rows = rows;
+    L.jobs_off = align256(sizeof(WsHeader));
+    L.sums_off = align256(L.jobs_off + (size_t)n_jobs * sizeof(JobDev));
+    L.offs_off = align256(L.sums_off + (size_t)(tiles + 1) * sizeof(int64_t));
+    L.counts_off = align256(L.offs_off + (size_t)(tiles + 1) * sizeof(int64_t));
+    L.total = align256(L.counts_off + (size_t)rows * sizeof(int32_t));
+    return L;
+}
+
+// ------------------------------------------------------------------------ kernels
+
+constexpr int JOBS_PER_PACK = 3800 / (int)sizeof(JobDev);
+struct JobPack {
+    int32_t count;
+    int32_t first;
+    JobDev jobs[JOBS_PER_PACK];
+};
+
+// Kernel arguments are copied at launch (and into a graph node at capture), so the
+// job table reaches the device without a host buffer that has to outlive the call.
+__global__ void k_put_jobs(JobDev *dst, JobPack pack) {
+    const int words = (int)(sizeof(JobDev) / sizeof(uint64_t)) * pack.count;
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(pack.jobs);
+    uint64_t *out = reinterpret_cast<uint64_t *>(dst + pack.first);
+    for (int w = threadIdx.x; w < words; w += blockDim.x) out[w] = src[w];
+}
+
+__global__ void k_clear_status(WsHeader *h) {
+    if (threadIdx.x == 0) h->status = PCT_OK;
+}
+
+__device__ __forceinline__ void set_status(int32_t *status, int32_t code) {
+    atomicCAS(status, PCT_OK, code);
+}
+
+// Tile -> job: jobs are laid out in tile order; binary search on tile_base.
+__device__ __forceinline__ int job_of_tile(const JobDev *jobs, int n_jobs, int64_t tile) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
+    // wave reduce, then across the 4 waves of a 256-thread block
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    int64_t s = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lds[w];
+    return s;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs, int n_jobs,
+                                                int32_t *__restrict__ counts, int64_t *__restrict__ tile_sums) {
+    __shared__ int64_t red[TILE / 64];
+    const int64_t tile = blockIdx.x;
+    const int jid = job_of_tile(jobs, n_jobs, tile);
+    const JobDev &J = jobs[jid];
+    const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
+    int64_t cnt = 0;
+    if (r < J.row_count) {
+        CountSink s;
+        trace_any<R>(J, J.row_begin + r, s);
+        cnt = s.n;
+        counts[J.count_off + r] = (int32_t)cnt;
+    }
+    const int64_t tot = block_sum_i64(cnt, red);
+    if (threadIdx.x == 0) tile_sums[tile] = tot;
+}
+
+// Exclusive scan of all tile sums (one block): offs[t] = sum of sums[0..t), offs[T] = total.
+// Each job's row_ptr is relative to offs[tile_base]; its total goes to nnz_total and
+// row_ptr[row_count].
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_tiles(const JobDev *__restrict__ jobs, int n_jobs,
+                                                             int64_t T, const int64_t *__restrict__ sums,
+                                                             int64_t *__restrict__ offs,
+                                                             int64_t *__restrict__ nnz_total) {
+    __shared__ int64_t part[SCAN_THREADS];
+    const int64_t per = (T + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    const int64_t b1 = (b0 + per < T) ? b0 + per : T;
+    int64_t acc = 0;
+    for (int64_t t = b0; t < b1; ++t) acc += sums[t];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the partials
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+        const int64_t v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = part[threadIdx.x] - acc;
+    for (int64_t t = b0; t < b1; ++t) {
+        offs[t] = run;
+        run += sums[t];
+    }
+    if (threadIdx.x == SCAN_THREADS - 1) offs[T] = part[SCAN_THREADS - 1];
+    __threadfence_block();
+    __syncthreads();
+    for (int j = threadIdx.x; j < n_jobs; j += SCAN_THREADS) {
+        const JobDev &J = jobs[j];
+        const int64_t tot = offs[J.tile_base + J.n_tiles] - offs[J.tile_base];
+        nnz_total[j] = tot;
+        J.row_ptr[J.row_count] = tot;
+    }
+}
+
+// row_ptr[r] = (offset of the tile within its job) + exclusive scan of the tile's counts.
+__global__ void __launch_bounds__(TILE) k_row_ptr(const JobDev *__restrict__ jobs, int n_jobs,
+                                                  const int32_t *__restrict__ counts,
+                                                  const int64_t *__restrict__ offs) {
+    __shared__ int64_t sc[TILE];
+    const int64_t tile = blockIdx.x;
+    const int jid = job_of_tile(jobs, n_jobs, tile);
+    const JobDev &J = jobs[jid];
+    const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
+    const int64_t c = (r < J.row_count) ? counts[J.count_off + r] : 0;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < TILE; off <<= 1) {
+        const int64_t v = (threadIdx.x >= (unsigned)off) ? sc[threadIdx.x - off] : 0;
+        __syncthreads();
+        sc[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (r < J.row_count) J.row_ptr[r] = offs[tile] - offs[J.tile_base] + sc[threadIdx.x] - c;
+}
+
+template <typename R, bool STORE>
+__global__ void __launch_bounds__(TILE) k_emit(const JobDev *__restrict__ jobs, int n_jobs,
+                                               int32_t *__restrict__ status) {
+    using TW = typename std::conditional<std::is_same<R, double>::value, double, float>::type;
+    const int64_t tile = blockIdx.x;
+    const int jid = job_of_tile(jobs, n_jobs, tile);
+    const JobDev &J = jobs[jid];
+    const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
+    if (r >= J.row_count) return;
+    EmitSink<R, TW> s;
+    s.cols = J.cols;
+    s.vals = J.vals;
+    s.x = J.x;
+    s.half = (J.val_dtype == PCT_F16);
+    s.store = STORE;
+    s.want_b = (J.b != nullptr);
+    if (STORE) {
+        s.pos = J.row_ptr[r];
+        s.end = J.row_ptr[r + 1];
+        if (s.pos < 0 || s.end < s.pos || s.end > J.cap) {
+            s.store = false;
+            set_status(status, PCT_ECAPACITY);
+        }
+    } else {
+        s.pos = 0;
+        s.end = 0;
+    }
+    const int64_t start = s.pos;
+    const int64_t g = J.row_begin + r;
+    trace_any<R>(J, g, s);
+    s.flush();
+    if (STORE && s.pos != s.end) set_status(status, PCT_EINTERNAL);
+    (void)start;
+    if (s.want_b) {
+        TW b = s.wepl;
+        if (J.noise > 0.0) {
+            R z1, z2;
+            normal_pair<R>(J.seed, 4, (uint64_t)g, z1, z2);
+            b = b * (TW(1) + TW(J.noise) * TW(z1));
+        }
+        J.b[r] = (float)b;
+    }
+}
+
+// ---------------------------------------------------------------- phantom build
+struct RegionDev {
+    int32_t axes;   // 2: ellipse / cylinder, 3: ellipsoid
+    float rsp;
+    double c[3], s[3];
+};
+struct PhantomArgs {
+    int32_t dim, voxelize, n_regions, pad;
+    int32_t n[3];
+    double h[3], o[3];
+    RegionDev reg[PCT_MAX_REGIONS];
+};
+
+__device__ __forceinline__ double rsp_at(const PhantomArgs &A, const double p[3]) {
+    double v = 0.0;
+    for (int k = 0; k < A.n_regions; ++k) {
+        const RegionDev &g = A.reg[k];
+        double q = 0.0;
+        for (int i = 0; i < g.axes; ++i) {
+            const double u = (p[i] - g.c[i]) / g.s[i];
+            q += u * u;
+        }
+        if (q <= 1.0) v = (double)g.rsp;
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_phantom(PhantomArgs A, float *__restrict__ x, int64_t nvox) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nvox) return;
+    int idx[3];
+    idx[0] = (int)(j % A.n[0]);
+    idx[1] = (int)((j / A.n[0]) % A.n[1]);
+    idx[2] = (int)(j / ((int64_t)A.n[0] * A.n[1]));
+    double val;
+    if (A.voxelize == PCT_CENTER) {
+        double p[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < A.dim; ++d) p[d] = A.o[d] + ((double)idx[d] + 0.5) * A.h[d];
+        val = rsp_at(A, p);
+    } else {
+        const int nc = 1 << A.dim;
+        double sum = 0.0;
+        for (int c = 0; c < nc; ++c) {
+            double p[3] = {0.0, 0.0, 0.0};
+            for (int d = 0; d < A.dim; ++d) p[d] = A.o[d] + (double)(idx[d] + ((c >> d) & 1)) * A.h[d];
+            sum += rsp_at(A, p);
+        }
+        val = sum / (double)nc;
+    }
+    x[j] = (float)val;
+}
+
+// ------------------------------------------------------------------ host helpers
+
+static bool finite_d(double v) { return isfinite(v) != 0; }
+
+static pct_status check_phantom(const pct_phantom *ph) {
+    if (!ph) return PCT_EINVAL;
+    if (ph->dim != 2 && ph->dim != 3) return PCT_EINVAL;
+    if (ph->n_regions < 1 || ph->n_regions > PCT_MAX_REGIONS || !ph->regions) return PCT_EINVAL;
+    if (ph->voxelize != PCT_CORNER_AVG && ph->voxelize != PCT_CENTER) return PCT_EINVAL;
+    int64_t nv = 1;
+    for (int d = 0; d < ph->dim; ++d) {
+        if (ph->n[d] < 1) return PCT_EINVAL;
+        if (!(ph->h[d] > 0.0) || !finite_d(ph->h[d]) || !finite_d(ph->origin[d])) return PCT_EINVAL;
+        nv *= ph->n[d];
+        if (nv >= ((int64_t)1 << 31)) return PCT_ERANGE;
+    }
+    for (int k = 0; k < ph->n_regions; ++k) {
+        const pct_region &r = ph->regions[k];
+        if (r.shape != PCT_ELLIPSE && r.shape != PCT_ELLIPSOID) return PCT_EINVAL;
+        if (!(r.rsp >= 0.0f) || !isfinite(r.rsp)) return PCT_EINVAL;
+        const int na = (r.shape == PCT_ELLIPSOID && ph->dim == 3) ? 3 : 2;
+        for (int i = 0; i < na; ++i) {
+            if (!(r.semi[i] > 0.0) || !finite_d(r.semi[i]) || !finite_d(r.center[i])) return PCT_EINVAL;
+        }
+    }
+    return PCT_OK;
+}
+
+static int64_t n_voxels(const pct_phantom *ph) {
+    int64_t nv = 1;
+    for (int d = 0; d < ph->dim; ++d) nv *= ph->n[d];
+    return nv;
+}
+
+static pct_status check_beam(const pct_beam *b) {
+    if (!b) return PCT_EINVAL;
+    if (b->n_angles < 1 || b->n_protons < 0) return PCT_EINVAL;
+    if (b->row_begin < 0 || b->row_count < 0 || b->row_begin + b->row_count > b->n_protons) return PCT_EINVAL;
+    if (b->path != PCT_STRAIGHT && b->path != PCT_HERMITE) return PCT_EINVAL;
+    const double f[] = {b->angle0_deg, b->dangle_deg, b->t_range[0], b->t_range[1], b->v_range[0],
+                        b->v_range[1], b->sigma_in_rad, b->sigma_out_rad, b->sigma_lat_mm, b->rho,
+                        b->step_mm, b->noise_rel};
+    for (double v : f)
+        if (!finite_d(v)) return PCT_EINVAL;
+    if (b->t_range[0] > b->t_range[1] || b->v_range[0] > b->v_range[1]) return PCT_EINVAL;
+    if (b->sigma_in_rad < 0 || b->sigma_out_rad < 0 || b->sigma_lat_mm < 0 || b->noise_rel < 0) return PCT_EINVAL;
+    if (b->rho < -1.0 || b->rho > 1.0) return PCT_EINVAL;
+    if (b->sigma_in_rad > 0.1 || b->sigma_out_rad > 0.1) return PCT_EINVAL;
+    if (b->path == PCT_HERMITE && !(b->step_mm > 0.0)) return PCT_EINVAL;
+    // (g + 1) * K must not overflow int64 in the row decode
+    if (b->n_protons > 0 && (double)b->n_protons * (double)b->n_angles > 9.0e18) return PCT_ERANGE;
+    return PCT_OK;
+}
+
+static pct_status check_jobs(int32_t n_jobs, const pct_job *jobs, bool need_csr, bool need_b) {
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return PCT_EINVAL;
+    for (int j = 0; j < n_jobs; ++j) {
+        const pct_job &jb = jobs[j];
+        pct_status st = check_phantom(jb.phantom);
+        if (st != PCT_OK) return st;
+        st = check_beam(jb.beam);
+        if (st != PCT_OK) return st;
+        if (jb.val_dtype != PCT_F32 && jb.val_dtype != PCT_F16) return PCT_EINVAL;
+        if (jb.precision != PCT_MIXED && jb.precision != PCT_PLAIN_F32) return PCT_EINVAL;
+        if (jb.precision != jobs[0].precision) return PCT_EINVAL;
+        if (jb.nnz_capacity < 0) return PCT_EINVAL;
+        if (!jb.x_dev && (need_b || jb.b_dev)) return PCT_EINVAL;
+        if (need_csr && !jb.row_ptr_dev) return PCT_EINVAL;
+        if (need_csr && jb.nnz_capacity > 0 && (!jb.cols_dev || !jb.vals_dev)) return PCT_EINVAL;
+        if (need_b && !jb.b_dev) return PCT_EINVAL;
+        if (jb.beam->path == PCT_HERMITE) {
+            // bound on the spline sample count: entry and exit lie on the outer boundary and
+            // the entry direction is within atan(tan(1.2)) of the beam axis (|sigma z| <= 1.2),
+            // so the chord is at most 3 outer diameters (cylinder) -- keep per-row work finite
+            const pct_region &o = jb.phantom->regions[0];
+            double smax = 0.0;
+            for (int i = 0; i < 3; ++i)
+                if (i < 2 || (o.shape == PCT_ELLIPSOID && jb.phantom->dim == 3)) smax = fmax(smax, o.semi[i]);
+            if (6.0 * smax / jb.beam->step_mm > (double)(1 << 22)) return PCT_ERANGE;
+        }
+    }
+    return PCT_OK;
+}
+
+static JobDev make_job(const pct_job &jb, int64_t count_off, int64_t tile_base) {
+    const pct_phantom &ph = *jb.phantom;
+    const pct_beam &bm = *jb.beam;
+    JobDev J;
+    memset(&J, 0, sizeof J);
+    J.dim = ph.dim;
+    J.path = bm.path;
+    J.val_dtype = jb.val_dtype;
+    const pct_region &o = ph.regions[0];
+    J.outer_axes = (o.shape == PCT_ELLIPSOID && ph.dim == 3) ? 3 : 2;
+    for (int d = 0; d < 3; ++d) {
+        const bool on = d < ph.dim;
+        J.n[d] = on ? ph.n[d] : 1;
+        J.h[d] = on ? ph.h[d] : 1.0;
+        J.invh[d] = 1.0 / J.h[d];
+        J.o[d] = on ? ph.origin[d] : 0.0;
+        J.top[d] = J.o[d] + (double)J.n[d] * J.h[d];
+        J.oc[d] = o.center[d];
+        J.inv_s2[d] = (d < J.outer_axes) ? 1.0 / (o.semi[d] * o.semi[d]) : 0.0;
+    }
+    J.K = bm.n_angles;
+    J.seed = bm.seed;
+    J.angle0 = bm.angle0_deg;
+    J.dangle = bm.dangle_deg;
+    J.P = bm.n_protons;
+    J.row_begin = bm.row_begin;
+    J.row_count = bm.row_count;
+    J.t_lo = bm.t_range[0];
+    J.t_span = bm.t_range[1] - bm.t_range[0];
+    J.v_lo = bm.v_range[0];
+    J.v_span = bm.v_range[1] - bm.v_range[0];
+    J.sig_in = bm.sigma_in_rad;
+    J.sig_out = bm.sigma_out_rad;
+    J.sig_lat = bm.sigma_lat_mm;
+    J.rho = bm.rho;
+    J.crho = sqrt(1.0 - bm.rho * bm.rho);
+    J.step = bm.step_mm;
+    J.noise = bm.noise_rel;
+    J.x = jb.x_dev;
+    J.row_ptr = jb.row_ptr_dev;
+    J.cols = jb.cols_dev;
+    J.vals = jb.vals_dev;
+    J.b = jb.b_dev;
+    J.cap = jb.nnz_capacity;
+    J.count_off = count_off;
+    J.tile_base = tile_base;
+    J.n_tiles = (bm.row_count + TILE - 1) / TILE;
+    return J;
+}
+
+struct Prepared {
+    Layout L;
+    std::vector<JobDev> jobs;
+};
+
+static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, Prepared &P,
+                          hipStream_t st) {
+    std::vector<int64_t> rc(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) rc[j] = jobs[j].beam->row_count;
+    P.L = layout_of(n_jobs, rc.data());
+    if (!ws || ws_bytes < P.L.total) return PCT_EWORKSPACE;
+    P.jobs.resize(n_jobs);
+    int64_t count_off = 0, tile_base = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        P.jobs[j] = make_job(jobs[j], count_off, tile_base);
+        count_off += rc[j];
+        tile_base += P.jobs[j].n_tiles;
+    }
+    JobDev *dst = reinterpret_cast<JobDev *>((char *)ws + P.L.jobs_off);
+    for (int first = 0; first < n_jobs; first += JOBS_PER_PACK) {
+        JobPack pack;
+        memset(&pack, 0, sizeof pack);
+        pack.first = first;
+        pack.count = (n_jobs - first < JOBS_PER_PACK) ? n_jobs - first : JOBS_PER_PACK;
+        for (int k = 0; k < pack.count; ++k) pack.jobs[k] = P.jobs[first + k];
+        hipLaunchKernelGGL(k_put_jobs, dim3(1), dim3(256), 0, st, dst, pack);
+    }
+    return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
+}
+
+}  // namespace pct
+
+using namespace pct;
+
+extern "C" {
+
+const char *pct_status_string(pct_status s) {
+    switch (s) {
+        case PCT_OK: return "PCT_OK";
+        case PCT_EINVAL: return "PCT_EINVAL: invalid descriptor";
+        case PCT_ERANGE: return "PCT_ERANGE: size overflows the index types";
+        case PCT_ECAPACITY: return "PCT_ECAPACITY: row did not fit in nnz_capacity";
+        case PCT_EWORKSPACE: return "PCT_EWORKSPACE: workspace missing or too small";
+        case PCT_EHIP: return "PCT_EHIP: HIP runtime error";
+        case PCT_EINTERNAL: return "PCT_EINTERNAL: emitted entries differ from the count";
+        default: return "unknown pct status";
+    }
+}
+
+int32_t pct_version(void) { return 100; }
+
+pct_status pct_phantom_build(const pct_phantom *ph, float *x_dev, void *stream) {
+    pct_status st = check_phantom(ph);
+    if (st != PCT_OK) return st;
+    if (!x_dev) return PCT_EINVAL;
+    PhantomArgs A;
+    memset(&A, 0, sizeof A);
+    A.dim = ph->dim;
+    A.voxelize = ph->voxelize;
+    A.n_regions = ph->n_regions;
+    for (int d = 0; d < 3; ++d) {
+        A.n[d] = d < ph->dim ? ph->n[d] : 1;
+        A.h[d] = d < ph->dim ? ph->h[d] : 1.0;
+        A.o[d] = d < ph->dim ? ph->origin[d] : 0.0;
+    }
+    for (int k = 0; k < ph->n_regions; ++k) {
+        const pct_region &r = ph->regions[k];
+        A.reg[k].axes = (r.shape == PCT_ELLIPSOID && ph->dim == 3) ? 3 : 2;
+        A.reg[k].rsp = r.rsp;
+        for (int i = 0; i < 3; ++i) {
+            A.reg[k].c[i] = r.center[i];
+            A.reg[k].s[i] = r.semi[i];
+        }
+    }
+    const int64_t nv = n_voxels(ph);
+    const int64_t blocks = (nv + 255) / 256;
+    hipLaunchKernelGGL(k_phantom, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, A, x_dev, nv);
+    return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
+}
+
+size_t pct_workspace_bytes(int32_t n_jobs, const pct_job *jobs) {
+    if (check_jobs(n_jobs, jobs, false, false) != PCT_OK) return 0;
+    std::vector<int64_t> rc(n_jobs > 0 ? n_jobs : 1);
+    for (int j = 0; j < n_jobs; ++j) rc[j] = jobs[j].beam->row_count;
+    return layout_of(n_jobs, rc.data()).total;
+}
+
+pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes,
+                          int64_t *nnz_total_dev, void *stream) {
+    pct_status st = check_jobs(n_jobs, jobs, true, false);
+    if (st != PCT_OK) return st;
+    if (n_jobs > 0 && !nnz_total_dev) return PCT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (!ws) return PCT_EWORKSPACE;
+    Prepared P;
+    st = prepare(n_jobs, jobs, ws, ws_bytes, P, s);
+    if (st != PCT_OK) return st;
+    char *w = (char *)ws;
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, (WsHeader *)w);
+    if (n_jobs == 0) return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
+    const JobDev *J = (const JobDev *)(w + P.L.jobs_off);
+    int64_t *sums = (int64_t *)(w + P.L.sums_off);
+    int64_t *offs = (int64_t *)(w + P.L.offs_off);
+    int32_t *counts = (int32_t *)(w + P.L.counts_off);
+    const int64_t T = P.L.total_tiles;
+    if (T > 0) {
+        if (jobs[0].precision == PCT_MIXED)
+            hipLaunchKernelGGL(k_count<double>, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums);
+        else
+            hipLaunchKernelGGL(k_count<float>, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums);
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_THREADS), 0, s, J, n_jobs, T, sums, offs, nnz_total_dev);
+    if (T > 0) hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, offs);
+    return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
+}
+
+static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, void *stream,
+                              bool store) {
+    pct_status st = check_jobs(n_jobs, jobs, store, !store);
+    if (st != PCT_OK) return st;
+    if (n_jobs == 0) return PCT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (!ws) return PCT_EWORKSPACE;
+    Prepared P;
+    st = prepare(n_jobs, jobs, ws, ws_bytes, P, s);
+    if (st != PCT_OK) return st;
+    char *w = (char *)ws;
+    const JobDev *J = (const JobDev *)(w + P.L.jobs_off);
+    int32_t *status = &((WsHeader *)w)->status;
+    const int64_t T = P.L.total_tiles;
+    if (T == 0) return PCT_OK;
+    const bool mixed = jobs[0].precision == PCT_MIXED;
+    if (store) {
+        if (mixed) hipLaunchKernelGGL((k_emit<double, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, status);
+        else hipLaunchKernelGGL((k_emit<float, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, status);
+    } else {
+        if (mixed) hipLaunchKernelGGL((k_emit<double, false>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, status);
+        else hipLaunchKernelGGL((k_emit<float, false>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, status);
+    }
+    return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
+}
+
+pct_status pct_emit_csr(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, void *stream) {
+    return emit_common(n_jobs, jobs, ws, ws_bytes, stream, true);
+}
+
+pct_status pct_wepl(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, void *stream) {
+    return emit_common(n_jobs, jobs, ws, ws_bytes, stream, false);
+}
+
+pct_status pct_device_status(const void *ws, void *stream) {
+    if (!ws) return PCT_EWORKSPACE;
+    int32_t v = PCT_OK;
+    if (hipMemcpyAsync(&v, ws, sizeof v, hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess) return PCT_EHIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PCT_EHIP;
+    return v;
+}
+
+}  // extern "C"

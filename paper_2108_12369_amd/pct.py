@@ -1,0 +1,269 @@
+"""Thin ctypes binding of libpct.so (the C ABI declared in include/pct.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP kernels of the
+library.  torch provides device memory and the stream.  If the library is missing the
+binding raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpct.so")
+
+PCT_OK, PCT_EINVAL, PCT_ERANGE, PCT_ECAPACITY, PCT_EWORKSPACE, PCT_EHIP, PCT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+PCT_ELLIPSE, PCT_ELLIPSOID = 0, 1
+PCT_CORNER_AVG, PCT_CENTER = 0, 1
+PCT_STRAIGHT, PCT_HERMITE = 0, 1
+PCT_F32, PCT_F16 = 0, 1
+PCT_MIXED, PCT_PLAIN_F32 = 0, 1
+PCT_MAX_REGIONS = 16
+
+SHAPES = {"ellipse": PCT_ELLIPSE, "ellipsoid": PCT_ELLIPSOID}
+VOXELIZE = {"corner_avg": PCT_CORNER_AVG, "center": PCT_CENTER}
+PATHS = {"straight": PCT_STRAIGHT, "hermite": PCT_HERMITE}
+VAL_DTYPES = {"f32": PCT_F32, "f16": PCT_F16}
+PRECISIONS = {"mixed": PCT_MIXED, "plain_f32": PCT_PLAIN_F32}
+
+SYMBOLS = ("pct_status_string", "pct_version", "pct_phantom_build", "pct_workspace_bytes",
+           "pct_count_rows", "pct_emit_csr", "pct_wepl", "pct_device_status")
+
+
+class PctError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class Region(C.Structure):
+    _fields_ = [("shape", C.c_int32), ("rsp", C.c_float), ("center", C.c_double * 3),
+                ("semi", C.c_double * 3)]
+
+
+class Phantom(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double * 3),
+                ("origin", C.c_double * 3), ("n_regions", C.c_int32), ("voxelize", C.c_int32),
+                ("regions", C.POINTER(Region))]
+
+
+class Beam(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("n_angles", C.c_int32), ("path", C.c_int32),
+                ("angle0_deg", C.c_double), ("dangle_deg", C.c_double), ("n_protons", C.c_int64),
+                ("row_begin", C.c_int64), ("row_count", C.c_int64), ("t_range", C.c_double * 2),
+                ("v_range", C.c_double * 2), ("sigma_in_rad", C.c_double),
+                ("sigma_out_rad", C.c_double), ("sigma_lat_mm", C.c_double), ("rho", C.c_double),
+                ("step_mm", C.c_double), ("noise_rel", C.c_double)]
+
+
+class Job(C.Structure):
+    _fields_ = [("phantom", C.POINTER(Phantom)), ("beam", C.POINTER(Beam)), ("x_dev", C.c_void_p),
+                ("row_ptr_dev", C.c_void_p), ("cols_dev", C.c_void_p), ("vals_dev", C.c_void_p),
+                ("nnz_capacity", C.c_int64), ("b_dev", C.c_void_p), ("val_dtype", C.c_int32),
+                ("precision", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpct.so; raise if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2108_12369_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        L.pct_status_string.argtypes = [C.c_int32]
+        L.pct_status_string.restype = C.c_char_p
+        L.pct_version.restype = C.c_int32
+        L.pct_phantom_build.argtypes = [C.POINTER(Phantom), C.c_void_p, C.c_void_p]
+        L.pct_phantom_build.restype = C.c_int32
+        L.pct_workspace_bytes.argtypes = [C.c_int32, C.POINTER(Job)]
+        L.pct_workspace_bytes.restype = C.c_size_t
+        for name in ("pct_emit_csr", "pct_wepl"):
+            getattr(L, name).argtypes = [C.c_int32, C.POINTER(Job), C.c_void_p, C.c_size_t, C.c_void_p]
+            getattr(L, name).restype = C.c_int32
+        L.pct_count_rows.argtypes = [C.c_int32, C.POINTER(Job), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
+        L.pct_count_rows.restype = C.c_int32
+        L.pct_device_status.argtypes = [C.c_void_p, C.c_void_p]
+        L.pct_device_status.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().pct_status_string(int(s)).decode()
+
+
+def _check(s: int, what: str):
+    if s != PCT_OK:
+        raise PctError(s, what)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+# ------------------------------------------------------------------ descriptors
+
+def make_phantom(ph: dict):
+    regs = ph["regions"]
+    arr = (Region * max(1, len(regs)))()
+    for i, r in enumerate(regs):
+        arr[i].shape = SHAPES[r["shape"]]
+        arr[i].rsp = float(r["rsp"])
+        arr[i].center[:] = [float(v) for v in list(r["center"]) + [0.0] * (3 - len(r["center"]))]
+        arr[i].semi[:] = [float(v) for v in list(r["semi"]) + [1.0] * (3 - len(r["semi"]))]
+    p = Phantom()
+    dim = int(ph["dim"])
+    n = list(ph["n"]) + [1] * (3 - len(ph["n"]))
+    h = list(ph["h"]) + [1.0] * (3 - len(ph["h"]))
+    p.dim = dim
+    p.n[:] = [int(v) for v in n]
+    p.h[:] = [float(v) for v in h]
+    if ph.get("origin") is not None:
+        o = list(ph["origin"]) + [0.0] * (3 - len(ph["origin"]))
+    else:
+        o = [-(n[d] * h[d]) / 2.0 if d < dim else 0.0 for d in range(3)]
+    p.origin[:] = [float(v) for v in o]
+    p.n_regions = len(regs)
+    p.voxelize = VOXELIZE[ph.get("voxelize", "corner_avg")]
+    p.regions = C.cast(arr, C.POINTER(Region))
+    return p, arr
+
+
+def make_beam(bm: dict, row_begin: int = 0, row_count: int | None = None) -> Beam:
+    b = Beam()
+    b.seed = int(bm["seed"])
+    b.n_angles = int(bm["n_angles"])
+    b.path = PATHS[bm.get("path", "straight")]
+    b.angle0_deg = float(bm.get("angle0_deg", 0.0))
+    b.dangle_deg = float(bm["dangle_deg"])
+    b.n_protons = int(bm["n_protons"])
+    b.row_begin = int(row_begin)
+    b.row_count = int(bm["n_protons"]) - int(row_begin) if row_count is None else int(row_count)
+    b.t_range[:] = [float(v) for v in bm["t_range"]]
+    b.v_range[:] = [float(v) for v in bm.get("v_range", (0.0, 0.0))]
+    b.sigma_in_rad = float(bm.get("sigma_in", 0.0))
+    b.sigma_out_rad = float(bm.get("sigma_out", 0.0))
+    b.sigma_lat_mm = float(bm.get("sigma_lat", 0.0))
+    b.rho = float(bm.get("rho", 0.0))
+    b.step_mm = float(bm.get("step", 0.25))
+    b.noise_rel = float(bm.get("noise_rel", 0.0))
+    return b
+
+
+def n_voxels(ph: dict) -> int:
+    n = list(ph["n"]) + [1] * (3 - len(ph["n"]))
+    return int(n[0]) * int(n[1]) * (int(n[2]) if int(ph["dim"]) == 3 else 1)
+
+
+# ------------------------------------------------------------------ entry points
+
+def phantom_build(ph: dict, x: torch.Tensor | None = None, stream=None, device="cuda") -> torch.Tensor:
+    """pct_phantom_build: voxelised true RSP vector x (float32, device)."""
+    if x is None:
+        x = torch.empty(n_voxels(ph), dtype=torch.float32, device=device)
+    p, keep = make_phantom(ph)
+    _check(lib().pct_phantom_build(C.byref(p), _ptr(x), _stream_ptr(stream)), "pct_phantom_build")
+    return x
+
+
+class JobSet:
+    """The job descriptors of one call, with the ctypes objects kept alive."""
+
+    def __init__(self):
+        self._keep = []
+        self.entries = []
+
+    def add(self, ph: dict, bm: dict, x, row_ptr=None, cols=None, vals=None, b=None,
+            nnz_capacity=0, val_dtype="f32", precision="mixed", row_begin=0, row_count=None):
+        p, arr = make_phantom(ph)
+        be = make_beam(bm, row_begin, row_count)
+        self._keep += [p, arr, be]
+        j = Job()
+        j.phantom = C.pointer(p)
+        j.beam = C.pointer(be)
+        j.x_dev = _ptr(x)
+        j.row_ptr_dev = _ptr(row_ptr)
+        j.cols_dev = _ptr(cols)
+        j.vals_dev = _ptr(vals)
+        j.nnz_capacity = int(nnz_capacity)
+        j.b_dev = _ptr(b)
+        j.val_dtype = VAL_DTYPES[val_dtype]
+        j.precision = PRECISIONS[precision]
+        self.entries.append(j)
+        return len(self.entries) - 1
+
+    def array(self):
+        arr = (Job * max(1, len(self.entries)))(*self.entries)
+        self._keep.append(arr)
+        return len(self.entries), arr
+
+
+def workspace_bytes(jobs: JobSet) -> int:
+    n, arr = jobs.array()
+    return int(lib().pct_workspace_bytes(n, arr))
+
+
+def count_rows(jobs: JobSet, ws: torch.Tensor, nnz_total: torch.Tensor, stream=None):
+    n, arr = jobs.array()
+    _check(lib().pct_count_rows(n, arr, _ptr(ws), ws.numel(), _ptr(nnz_total), _stream_ptr(stream)),
+           "pct_count_rows")
+
+
+def emit_csr(jobs: JobSet, ws: torch.Tensor, stream=None):
+    n, arr = jobs.array()
+    _check(lib().pct_emit_csr(n, arr, _ptr(ws), ws.numel(), _stream_ptr(stream)), "pct_emit_csr")
+
+
+def wepl(jobs: JobSet, ws: torch.Tensor, stream=None):
+    n, arr = jobs.array()
+    _check(lib().pct_wepl(n, arr, _ptr(ws), ws.numel(), _stream_ptr(stream)), "pct_wepl")
+
+
+def device_status(ws: torch.Tensor, stream=None) -> int:
+    return int(lib().pct_device_status(_ptr(ws), _stream_ptr(stream)))
+
+
+# ------------------------------------------------------------------ convenience
+
+def simulate(cfg: dict, row_begin: int = 0, row_count: int | None = None, precision: str = "mixed",
+             val_dtype: str | None = None, x: torch.Tensor | None = None, stream=None,
+             device="cuda") -> dict:
+    """Phantom build, count, scan and emit for one workload (or one chunk of its rows).
+
+    Returns device tensors x, row_ptr (int64), cols (int32), vals (float32/float16), b."""
+    ph, bm = cfg["phantom"], cfg["beam"]
+    val_dtype = val_dtype or cfg.get("val_dtype", "f32")
+    if row_count is None:
+        row_count = int(bm["n_protons"]) - row_begin
+    if x is None:
+        x = phantom_build(ph, stream=stream, device=device)
+    row_ptr = torch.empty(row_count + 1, dtype=torch.int64, device=device)
+    js = JobSet()
+    js.add(ph, bm, x, row_ptr=row_ptr, val_dtype=val_dtype, precision=precision,
+           row_begin=row_begin, row_count=row_count)
+    ws = torch.empty(max(workspace_bytes(js), 256), dtype=torch.uint8, device=device)
+    nnz_t = torch.empty(1, dtype=torch.int64, device=device)
+    count_rows(js, ws, nnz_t, stream)
+    nnz = int(nnz_t.item())
+    cols = torch.empty(max(nnz, 1), dtype=torch.int32, device=device)
+    vals = torch.empty(max(nnz, 1), dtype=torch.float16 if val_dtype == "f16" else torch.float32, device=device)
+    b = torch.empty(max(row_count, 1), dtype=torch.float32, device=device)
+    js2 = JobSet()
+    js2.add(ph, bm, x, row_ptr=row_ptr, cols=cols, vals=vals, b=b, nnz_capacity=nnz,
+            val_dtype=val_dtype, precision=precision, row_begin=row_begin, row_count=row_count)
+    emit_csr(js2, ws, stream)
+    st = device_status(ws, stream)
+    _check(st, "device status after pct_emit_csr")
+    return {"x": x, "row_ptr": row_ptr, "cols": cols[:nnz], "vals": vals[:nnz], "b": b[:row_count],
+            "nnz": nnz}

@@ -1,0 +1,200 @@
+"""The C ABI library on the host (no GPU work): it loads, exports every entry point the
+public header declares, its structs have the layout the binding assumes, and host-side
+validation rejects bad descriptors before anything would be enqueued."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pct.h")
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2108_12369_amd import pct
+    return pct
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pct_[a-z_]+)\s*\(", text)))
+
+
+def test_header_functions_exported(P):
+    names = _declared_functions()
+    assert set(names) == set(P.SYMBOLS)
+    lib = P.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(P):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        s = P.status_string(code)
+        assert s.startswith("PCT_")
+    assert P.lib().pct_version() >= 100
+
+
+def test_struct_layout_matches_header(P, tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "pct.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
+int main(void) {
+  printf("pct_region %zu\npct_phantom %zu\npct_beam %zu\npct_job %zu\n",
+         sizeof(pct_region), sizeof(pct_phantom), sizeof(pct_beam), sizeof(pct_job));
+  F(pct_region, rsp) F(pct_region, center) F(pct_region, semi)
+  F(pct_phantom, n) F(pct_phantom, h) F(pct_phantom, origin) F(pct_phantom, n_regions)
+  F(pct_phantom, voxelize) F(pct_phantom, regions)
+  F(pct_beam, n_angles) F(pct_beam, path) F(pct_beam, angle0_deg) F(pct_beam, n_protons)
+  F(pct_beam, row_begin) F(pct_beam, row_count) F(pct_beam, t_range) F(pct_beam, v_range)
+  F(pct_beam, sigma_in_rad) F(pct_beam, rho) F(pct_beam, step_mm) F(pct_beam, noise_rel)
+  F(pct_job, x_dev) F(pct_job, row_ptr_dev) F(pct_job, cols_dev) F(pct_job, vals_dev)
+  F(pct_job, nnz_capacity) F(pct_job, b_dev) F(pct_job, val_dtype) F(pct_job, precision)
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(line.split() for line in out if line.strip())
+    types = {"pct_region": P.Region, "pct_phantom": P.Phantom, "pct_beam": P.Beam, "pct_job": P.Job}
+    for k, v in got.items():
+        if "." in k:
+            t, m = k.split(".")
+            assert getattr(types[t], m).offset == int(v), k
+        else:
+            assert C.sizeof(types[k]) == int(v), k
+
+
+def test_workspace_bytes_scales_with_rows(P, W):
+    js = P.JobSet()
+    cfg = W.c0()
+    js.add(cfg["phantom"], cfg["beam"], None)
+    small = P.workspace_bytes(js)
+    js2 = P.JobSet()
+    js2.add(cfg["phantom"], cfg["beam"], None)
+    js2.add(cfg["phantom"], cfg["beam"], None)
+    assert small > 92160 * 4
+    assert P.workspace_bytes(js2) > small
+    assert P.workspace_bytes(P.JobSet()) > 0  # header only
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("dim", 4, -1), ("voxelize", 7, -1), ("n_regions", 0, -1), ("n_regions", 17, -1),
+    ("h0", 0.0, -1), ("h0", float("nan"), -1), ("n0", 0, -1), ("nvox", None, -2),
+    ("semi", -1.0, -1), ("rsp", -0.5, -1)])
+def test_phantom_validation(P, W, field, value, code):
+    ph = W.c0()["phantom"]
+    import copy
+    ph = copy.deepcopy(ph)
+    if field == "dim":
+        ph["dim"] = value
+    elif field == "voxelize":
+        ph["voxelize"] = "center"
+    elif field == "n_regions":
+        ph["regions"] = [] if value == 0 else ph["regions"] * 4
+    elif field == "h0":
+        ph["h"][0] = value
+    elif field == "n0":
+        ph["n"][0] = value
+    elif field == "nvox":
+        ph["dim"] = 3
+        ph["n"] = [2048, 2048, 1024]
+        ph["h"] = [0.1, 0.1, 0.1]
+    elif field == "semi":
+        ph["regions"][1]["semi"][0] = value
+    elif field == "rsp":
+        ph["regions"][2]["rsp"] = value
+    p, keep = P.make_phantom(ph)
+    if field == "voxelize":
+        p.voxelize = value
+    if field == "dim":
+        p.dim = value
+    assert P.lib().pct_phantom_build(C.byref(p), C.c_void_p(0), C.c_void_p(0)) == code
+    js = P.JobSet()
+    js.add(ph, W.c0()["beam"], None)
+    n, arr = js.array()
+    if field in ("voxelize", "dim"):
+        arr[0].phantom.contents.voxelize = p.voxelize
+        arr[0].phantom.contents.dim = p.dim
+    assert P.lib().pct_workspace_bytes(n, arr) == 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n_angles", 0), ("n_protons", -1), ("row_count", 10**9), ("row_begin", -5),
+    ("t_range", [1.0, -1.0]), ("sigma_in", -0.1), ("rho", 1.5), ("noise_rel", -0.01),
+    ("step", 0.0), ("path", "spiral"), ("sigma_out", float("inf"))])
+def test_beam_validation(P, W, field, value):
+    import copy
+    cfg = W.c1()
+    bm = copy.deepcopy(cfg["beam"])
+    row_begin, row_count = 0, None
+    if field == "row_count":
+        row_count = value
+    elif field == "row_begin":
+        row_begin = value
+    elif field == "path":
+        bm["path"] = "straight"
+    else:
+        bm[field] = value
+    js = P.JobSet()
+    js.add(cfg["phantom"], bm, None, row_begin=row_begin, row_count=row_count)
+    n, arr = js.array()
+    if field == "path":
+        arr[0].beam.contents.path = 9
+    assert P.lib().pct_workspace_bytes(n, arr) == 0
+    # the entry points reject it on the host, before anything is enqueued
+    assert P.lib().pct_count_rows(n, arr, None, 1 << 30, None, None) == -1
+
+
+def test_job_validation(P, W):
+    cfg = W.c0()
+    js = P.JobSet()
+    js.add(cfg["phantom"], cfg["beam"], None)
+    n, arr = js.array()
+    arr[0].val_dtype = 5
+    assert P.lib().pct_workspace_bytes(n, arr) == 0
+    arr[0].val_dtype = 0
+    arr[0].precision = 3
+    assert P.lib().pct_workspace_bytes(n, arr) == 0
+    arr[0].precision = 0
+    arr[0].nnz_capacity = -1
+    assert P.lib().pct_workspace_bytes(n, arr) == 0
+    arr[0].nnz_capacity = 0
+    # emit needs row_ptr; wepl needs b (and x)
+    assert P.lib().pct_emit_csr(n, arr, None, 1 << 30, None) == -1
+    assert P.lib().pct_wepl(n, arr, None, 1 << 30, None) == -1
+    # precision must agree across the jobs of one call
+    js2 = P.JobSet()
+    js2.add(cfg["phantom"], cfg["beam"], None)
+    js2.add(cfg["phantom"], cfg["beam"], None, precision="plain_f32")
+    n2, arr2 = js2.array()
+    assert P.lib().pct_workspace_bytes(n2, arr2) == 0
+    # a workspace that is missing or too small is refused before any launch
+    import torch
+    on_gpu = torch.cuda.is_available()
+    dev = (lambda nbytes: torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")) if on_gpu else None
+    keep = []
+
+    def ptr(nbytes):
+        if dev is None:
+            return C.c_void_p(1 << 20)  # never dereferenced: no device in this process
+        t = dev(nbytes)
+        keep.append(t)
+        return C.c_void_p(t.data_ptr())
+
+    js3 = P.JobSet()
+    js3.add(cfg["phantom"], cfg["beam"], None)
+    n3, arr3 = js3.array()
+    arr3[0].row_ptr_dev = ptr(8 * 92161).value
+    need = P.lib().pct_workspace_bytes(n3, arr3)
+    nnz = ptr(8)
+    assert P.lib().pct_count_rows(n3, arr3, ptr(need - 1), need - 1, nnz, None) == -4
+    assert P.lib().pct_count_rows(n3, arr3, None, need, nnz, None) == -4
