@@ -1,0 +1,266 @@
+"""Benchmark of the proton-CT hot path on one MI355X.
+
+One step = the whole path over one batch: phantom voxelisation (x), count pass, scan
+(row_ptr), emit pass (cols, vals and the WEPL b).  Outputs are allocated once before
+the timed region; nothing is read back inside it.
+
+Prints one JSON line: throughput in protons/s (whole job), nnz/s, the emit kernel's
+algorithmic HBM bandwidth against the 8 TB/s peak, the plain-FP32 form measured the
+same way, and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c1", help="c0 | c1 | c2 | c3 | c4 | paper")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample size (0: auto)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+class Pipeline:
+    """Pre-allocated buffers for a list of jobs (optionally split in row chunks)."""
+
+    def __init__(self, P, cfgs, precision="mixed", chunk_rows=None, val_dtype=None):
+        import torch
+        self.P, self.torch = P, torch
+        self.cfgs = cfgs
+        self.precision = precision
+        self.val_dtype = [val_dtype or c.get("val_dtype", "f32") for c in cfgs]
+        self.xs = [P.phantom_build(c["phantom"]) for c in cfgs]
+        # chunks: list of lists of (job index, row_begin, row_count)
+        if chunk_rows:
+            assert len(cfgs) == 1
+            n = cfgs[0]["beam"]["n_protons"]
+            self.chunks = [[(0, rb, min(chunk_rows, n - rb))] for rb in range(0, n, chunk_rows)]
+        else:
+            self.chunks = [[(j, 0, c["beam"]["n_protons"]) for j, c in enumerate(cfgs)]]
+        max_rows = {}
+        for ch in self.chunks:
+            for j, rb, rc in ch:
+                max_rows[j] = max(max_rows.get(j, 0), rc)
+        dev = "cuda"
+        self.row_ptr = {j: torch.empty(r + 1, dtype=torch.int64, device=dev) for j, r in max_rows.items()}
+        self.b = {j: torch.empty(max(r, 1), dtype=torch.float32, device=dev) for j, r in max_rows.items()}
+        ws_bytes = 0
+        for ch in self.chunks:
+            ws_bytes = max(ws_bytes, P.workspace_bytes(self._jobset(ch, count_only=True)))
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        self.nnz = torch.empty(len(cfgs), dtype=torch.int64, device=dev)
+        # size the outputs from a first count of every chunk
+        self.chunk_nnz = []
+        cap = {}
+        for ch in self.chunks:
+            P.count_rows(self._jobset(ch, count_only=True), self.ws, self.nnz)
+            nz = self.nnz.cpu().numpy()
+            self.chunk_nnz.append([int(nz[k]) for k in range(len(ch))])
+            for k, (j, rb, rc) in enumerate(ch):
+                cap[j] = max(cap.get(j, 0), int(nz[k]))
+        self.cols = {j: torch.empty(max(c, 1), dtype=torch.int32, device=dev) for j, c in cap.items()}
+        self.vals = {j: torch.empty(max(c, 1), dtype=torch.float16 if self.val_dtype[j] == "f16" else torch.float32,
+                                    device=dev) for j, c in cap.items()}
+        self.cap = cap
+        self.count_sets = [self._jobset(ch, count_only=True) for ch in self.chunks]
+        self.emit_sets = [self._jobset(ch, count_only=False) for ch in self.chunks]
+        self.total_rows = sum(rc for ch in self.chunks for _, _, rc in ch)
+        self.total_nnz = sum(sum(v) for v in self.chunk_nnz)
+
+    def _jobset(self, ch, count_only):
+        js = self.P.JobSet()
+        for j, rb, rc in ch:
+            c = self.cfgs[j]
+            if count_only:
+                js.add(c["phantom"], c["beam"], self.xs[j], row_ptr=self.row_ptr[j], val_dtype=self.val_dtype[j],
+                       precision=self.precision, row_begin=rb, row_count=rc)
+            else:
+                js.add(c["phantom"], c["beam"], self.xs[j], row_ptr=self.row_ptr[j], cols=self.cols[j],
+                       vals=self.vals[j], b=self.b[j], nnz_capacity=self.cap[j], val_dtype=self.val_dtype[j],
+                       precision=self.precision, row_begin=rb, row_count=rc)
+        js.array()
+        return js
+
+    def step(self, emit_events=None):
+        P = self.P
+        for j, c in enumerate(self.cfgs):
+            P.phantom_build(c["phantom"], self.xs[j])
+        for k in range(len(self.chunks)):
+            P.count_rows(self.count_sets[k], self.ws, self.nnz)
+            if emit_events is not None:
+                e0, e1 = self.torch.cuda.Event(enable_timing=True), self.torch.cuda.Event(enable_timing=True)
+                e0.record()
+                P.emit_csr(self.emit_sets[k], self.ws)
+                e1.record()
+                emit_events.append((e0, e1))
+            else:
+                P.emit_csr(self.emit_sets[k], self.ws)
+
+    def bytes_emit(self):
+        """Algorithmic HBM bytes of all emit launches of one step: cols (4 B) and
+        vals (2 or 4 B) per nnz written, b (4 B) per row written, row_ptr (8 B) per row read."""
+        tot = 0
+        for ch, nzs in zip(self.chunks, self.chunk_nnz):
+            for (j, rb, rc), nz in zip(ch, nzs):
+                vb = 2 if self.val_dtype[j] == "f16" else 4
+                tot += nz * (4 + vb) + rc * (4 + 8) + 8
+        return tot
+
+    def bytes_step(self):
+        """Algorithmic bytes of a whole step: emit bytes + x written + counts written and
+        read twice + row_ptr written."""
+        nvox = sum(self.P.n_voxels(c["phantom"]) for c in self.cfgs)
+        return self.bytes_emit() + 4 * nvox + self.total_rows * (4 * 3 + 8)
+
+
+def workload(name, W):
+    if name == "c3":
+        return W.c3_jobs(), None
+    cfg = W.by_name(name)
+    return [cfg], cfg.get("chunk_rows")
+
+
+def time_pipeline(pl, steps, warmup):
+    torch = pl.torch
+    for _ in range(warmup):
+        pl.step()
+    torch.cuda.synchronize()
+    events = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pl.step(events)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    emit_ms = [a.elapsed_time(b) for a, b in events]
+    st = pl.P.device_status(pl.ws)
+    if st != pl.P.PCT_OK:
+        raise RuntimeError(f"device status {pl.P.status_string(st)}")
+    return dt, emit_ms
+
+
+def cpu_baseline(cfgs, n_rows_target):
+    """The oracle, single-threaded, on evenly spaced rows of the same workload."""
+    from oracle import oracle as O
+    O.build(force=False)
+    total = sum(c["beam"]["n_protons"] for c in cfgs)
+    per = [max(1, int(round(n_rows_target * c["beam"]["n_protons"] / total))) for c in cfgs]
+    rows_done, nnz_done, secs = 0, 0, 0.0
+    for c, k in zip(cfgs, per):
+        n = c["beam"]["n_protons"]
+        rows = np.unique(np.linspace(0, n - 1, min(k, n)).astype(np.int64))
+        x = O.phantom_build(c["phantom"])
+        t0 = time.perf_counter()
+        r = O.run(c, rows=rows, x=x)
+        secs += time.perf_counter() - t0
+        rows_done += len(rows)
+        nnz_done += len(r["cols"])
+    return rows_done, nnz_done, secs
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "gpus_requested": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_2108_12369_amd import pct as P
+    from paper_2108_12369_amd import workloads as W
+
+    P.lib()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        n = 1 << 28  # 1 GiB of float32
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}))
+        return
+
+    cfgs, chunk = workload(args.workload, W)
+    pl = Pipeline(P, cfgs, "mixed", chunk)
+    dt, emit_ms = time_pipeline(pl, args.steps, args.warmup)
+    ms_step = 1e3 * dt / args.steps
+    rows = pl.total_rows
+    emit_launch_ms = float(np.mean(emit_ms)) / len(pl.chunks)
+    emit_bytes_launch = pl.bytes_emit() / len(pl.chunks)
+    achieved = emit_bytes_launch / (emit_launch_ms * 1e-3) / 1e9
+    res = {
+        "metric": "protons/s and CSR nnz/s (HBM GB/s % peak), batched mixed vs plain FP32",
+        "value": rows / (ms_step * 1e-3),
+        "unit": "protons/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "precision": "mixed: FP64 geometry and face ordering, FP32 lengths, FP64 WEPL sum, "
+                     + ("FP16" if pl.val_dtype[0] == "f16" else "FP32") + " stored lengths",
+        "data": "synthetic",
+        "config": {"workload": cfgs[0]["name"] if len(cfgs) == 1 else f"c3-batched-{len(cfgs)}-jobs",
+                   "jobs": len(cfgs), "rows": rows, "nnz": pl.total_nnz, "chunks": len(pl.chunks),
+                   "val_dtype": pl.val_dtype[0]},
+        "nnz_per_s": pl.total_nnz / (ms_step * 1e-3),
+        "step_algorithmic_GBps": pl.bytes_step() / (ms_step * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": "k_emit", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "emit_ms_per_launch": emit_launch_ms, "algorithmic_bytes_per_launch": emit_bytes_launch},
+    }
+    del pl
+    torch.cuda.empty_cache()
+
+    if not args.no_plain:
+        plf = Pipeline(P, cfgs, "plain_f32", chunk, val_dtype="f32")
+        dtp, emit_p = time_pipeline(plf, args.steps, args.warmup)
+        msp = 1e3 * dtp / args.steps
+        res["plain_f32"] = {"protons_per_s": plf.total_rows / (msp * 1e-3), "ms_per_step": msp,
+                            "nnz_per_s": plf.total_nnz / (msp * 1e-3),
+                            "emit_ms_per_launch": float(np.mean(emit_p)) / len(plf.chunks),
+                            "emit_GBps": plf.bytes_emit() / len(plf.chunks)
+                            / (float(np.mean(emit_p)) / len(plf.chunks) * 1e-3) / 1e9}
+        res["mixed_over_plain"] = res["value"] / res["plain_f32"]["protons_per_s"]
+        del plf
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        target = args.cpu_rows
+        if not target:
+            # size the sample for about 12 s of oracle time from a short probe
+            n0, _, s0 = cpu_baseline(cfgs, 1000)
+            target = max(1000, int(12.0 * n0 / max(s0, 1e-3)))
+        nrow, nnz, secs = cpu_baseline(cfgs, target)
+        res["cpu_baseline"] = {"value": nrow / secs, "unit": "protons/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{nrow} evenly spaced rows of the same workload ({nnz} nnz), "
+                                         f"single-threaded FP64 oracle, {secs:.1f} s",
+                               "nnz_per_s": nnz / secs, "host_cpus": os.cpu_count()}
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -137,8 +137,9 @@ pct_status pct_phantom_build(const pct_phantom *phantom, float *x_dev, void *str
 
 /* Bytes of device workspace that pct_count_rows / pct_emit_csr / pct_wepl need for
  * these jobs (0 if a descriptor is invalid).  The workspace holds the job table, the
- * per-row counts, the scan partials and a status word; its contents between calls
- * carry the status word only. */
+ * per-row counts, the scan partials, a description of every row's path and a status
+ * word.  pct_emit_csr reads the path descriptions that pct_count_rows wrote: pass it
+ * the same workspace and the same jobs (output pointers may differ). */
 size_t pct_workspace_bytes(int32_t n_jobs, const pct_job *jobs);
 
 /* Count pass: for every row of every job the number of CSR entries the path produces
@@ -148,7 +149,8 @@ size_t pct_workspace_bytes(int32_t n_jobs, const pct_job *jobs);
 pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_t ws_bytes,
                           int64_t *nnz_total_dev, void *stream);
 
-/* Emit pass: traverse every path again and write its entries at
+/* Emit pass (after pct_count_rows on the same jobs and workspace): walk every path and
+ * write its entries at
  * [row_ptr[r], row_ptr[r+1]) of cols_dev (voxel column) and vals_dev (path length in
  * that voxel, mm), in path order from entry to exit, and, if b_dev is not NULL, its
  * WEPL b[r] = sum of length * x[col] (with noise when noise_rel > 0).  row_ptr_dev must

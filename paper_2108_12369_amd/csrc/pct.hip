@@ -11,6 +11,7 @@
 //   pct_wepl          : k_put_jobs, k_emit  (no A stores) -> b
 #include "../../include/pct.h"
 #include "pct_device.h"
+#include "pct_wave.h"
 
 #include <math.h>
 #include <string.h>
@@ -22,7 +23,8 @@ namespace pct {
 constexpr int TILE = 256;            // rows per tile (= threads per block of k_count/k_emit)
 constexpr int SCAN_THREADS = 1024;
 
-// Workspace layout (bytes): [0,256) header | job table | tile sums | tile offsets | counts
+// Workspace layout (bytes): [0,256) header | job table | tile sums | tile offsets | counts |
+// per-row path descriptions
 struct WsHeader {
     int32_t status;
     int32_t pad[63];
@@ -31,9 +33,12 @@ struct WsHeader {
 static inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t jobs_off, sums_off, offs_off, counts_off, total;
+    size_t jobs_off, sums_off, offs_off, counts_off, rows_off, total;
     int64_t total_tiles, total_rows;
 };
+
+// per-row path descriptions (the larger of the two precisions)
+constexpr size_t ROWW_BYTES = sizeof(RowW<double>) > sizeof(RowW<float>) ? sizeof(RowW<double>) : sizeof(RowW<float>);
 
 static Layout layout_of(int32_t n_jobs, const int64_t *row_counts) {
     Layout L{};
@@ -48,7 +53,8 @@ static Layout layout_of(int32_t n_jobs, const int64_t *row_counts) {
     L.sums_off = align256(L.jobs_off + (size_t)n_jobs * sizeof(JobDev));
     L.offs_off = align256(L.sums_off + (size_t)(tiles + 1) * sizeof(int64_t));
     L.counts_off = align256(L.offs_off + (size_t)(tiles + 1) * sizeof(int64_t));
-    L.total = align256(L.counts_off + (size_t)rows * sizeof(int32_t));
+    L.rows_off = align256(L.counts_off + (size_t)rows * sizeof(int32_t));
+    L.total = align256(L.rows_off + (size_t)rows * ROWW_BYTES);
     return L;
 }
 
@@ -74,9 +80,7 @@ __global__ void k_clear_status(WsHeader *h) {
     if (threadIdx.x == 0) h->status = PCT_OK;
 }
 
-__device__ __forceinline__ void set_status(int32_t *status, int32_t code) {
-    atomicCAS(status, PCT_OK, code);
-}
+__device__ __forceinline__ void set_status(int32_t *status, int32_t code) { set_status_dev(status, code); }
 
 // Tile -> job: jobs are laid out in tile order; binary search on tile_base.
 __device__ __forceinline__ int job_of_tile(const JobDev *jobs, int n_jobs, int64_t tile) {
@@ -101,9 +105,12 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
     return s;
 }
 
-template <typename R>
+// Count pass (one lane per row): describe the row's path in the workspace and count its
+// CSR entries.  With COUNT false only the descriptions are written (WEPL-only calls).
+template <typename R, bool COUNT>
 __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs, int n_jobs,
-                                                int32_t *__restrict__ counts, int64_t *__restrict__ tile_sums) {
+                                                int32_t *__restrict__ counts, int64_t *__restrict__ tile_sums,
+                                                RowW<R> *__restrict__ rowbuf) {
     __shared__ int64_t red[TILE / 64];
     const int64_t tile = blockIdx.x;
     const int jid = job_of_tile(jobs, n_jobs, tile);
@@ -111,13 +118,19 @@ __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs,
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     int64_t cnt = 0;
     if (r < J.row_count) {
-        CountSink s;
-        trace_any<R>(J, J.row_begin + r, s);
-        cnt = s.n;
-        counts[J.count_off + r] = (int32_t)cnt;
+        RowW<R> &w = rowbuf[J.count_off + r];
+        const int64_t g = J.row_begin + r;
+        if (J.dim == 3) setup_row<R, 3>(J, g, w);
+        else setup_row<R, 2>(J, g, w);
+        if (COUNT) {
+            cnt = (J.dim == 3) ? count_row<R, 3>(J, w, g) : count_row<R, 2>(J, w, g);
+            counts[J.count_off + r] = (int32_t)cnt;
+        }
     }
-    const int64_t tot = block_sum_i64(cnt, red);
-    if (threadIdx.x == 0) tile_sums[tile] = tot;
+    if (COUNT) {
+        const int64_t tot = block_sum_i64(cnt, red);
+        if (threadIdx.x == 0) tile_sums[tile] = tot;
+    }
 }
 
 // Exclusive scan of all tile sums (one block): offs[t] = sum of sums[0..t), offs[T] = total.
@@ -179,48 +192,39 @@ __global__ void __launch_bounds__(TILE) k_row_ptr(const JobDev *__restrict__ job
     if (r < J.row_count) J.row_ptr[r] = offs[tile] - offs[J.tile_base] + sc[threadIdx.x] - c;
 }
 
+// Wave-cooperative emit: each wavefront of the block takes 64 rows of the tile.
+constexpr int KR2 = 2, KC2 = 4;   // ray cells / spline chords per lane per pass, 2D
+constexpr int KR3 = 2, KC3 = 2;   // ... 3D
+
 template <typename R, bool STORE>
-__global__ void __launch_bounds__(TILE) k_emit(const JobDev *__restrict__ jobs, int n_jobs,
-                                               int32_t *__restrict__ status) {
-    using TW = typename std::conditional<std::is_same<R, double>::value, double, float>::type;
+__global__ void __launch_bounds__(TILE) k_emit_wave(const JobDev *__restrict__ jobs, int n_jobs,
+                                                    const RowW<R> *__restrict__ rowbuf,
+                                                    int32_t *__restrict__ status) {
+    const int64_t tile = blockIdx.x;
+    const int jid = job_of_tile(jobs, n_jobs, tile);
+    const JobDev &J = jobs[jid];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x % WAVE;
+    const int64_t r0 = (tile - J.tile_base) * TILE + wave * WAVE;
+    const RowW<R> *rows = rowbuf + J.count_off;
+    if (J.dim == 3) emit_rows_wave<R, 3, KR3, KC3, STORE>(J, rows, r0, lane, status);
+    else emit_rows_wave<R, 2, KR2, KC2, STORE>(J, rows, r0, lane, status);
+}
+
+// Rows whose spline may leave the grid box: one lane per row.
+template <typename R, bool STORE>
+__global__ void __launch_bounds__(TILE) k_emit_lane(const JobDev *__restrict__ jobs, int n_jobs,
+                                                    const RowW<R> *__restrict__ rowbuf,
+                                                    int32_t *__restrict__ status) {
     const int64_t tile = blockIdx.x;
     const int jid = job_of_tile(jobs, n_jobs, tile);
     const JobDev &J = jobs[jid];
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     if (r >= J.row_count) return;
-    EmitSink<R, TW> s;
-    s.cols = J.cols;
-    s.vals = J.vals;
-    s.x = J.x;
-    s.half = (J.val_dtype == PCT_F16);
-    s.store = STORE;
-    s.want_b = (J.b != nullptr);
-    if (STORE) {
-        s.pos = J.row_ptr[r];
-        s.end = J.row_ptr[r + 1];
-        if (s.pos < 0 || s.end < s.pos || s.end > J.cap) {
-            s.store = false;
-            set_status(status, PCT_ECAPACITY);
-        }
-    } else {
-        s.pos = 0;
-        s.end = 0;
-    }
-    const int64_t start = s.pos;
-    const int64_t g = J.row_begin + r;
-    trace_any<R>(J, g, s);
-    s.flush();
-    if (STORE && s.pos != s.end) set_status(status, PCT_EINTERNAL);
-    (void)start;
-    if (s.want_b) {
-        TW b = s.wepl;
-        if (J.noise > 0.0) {
-            R z1, z2;
-            normal_pair<R>(J.seed, 4, (uint64_t)g, z1, z2);
-            b = b * (TW(1) + TW(J.noise) * TW(z1));
-        }
-        J.b[r] = (float)b;
-    }
+    const RowW<R> &w = rowbuf[J.count_off + r];
+    if (w.kind != 3) return;
+    if (J.dim == 3) emit_row_lane<R, 3, STORE>(J, w, r, status);
+    else emit_row_lane<R, 2, STORE>(J, w, r, status);
 }
 
 // ---------------------------------------------------------------- phantom build
@@ -516,9 +520,11 @@ pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
     const int64_t T = P.L.total_tiles;
     if (T > 0) {
         if (jobs[0].precision == PCT_MIXED)
-            hipLaunchKernelGGL(k_count<double>, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums);
+            hipLaunchKernelGGL((k_count<double, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums,
+                               (RowW<double> *)(w + P.L.rows_off));
         else
-            hipLaunchKernelGGL(k_count<float>, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums);
+            hipLaunchKernelGGL((k_count<float, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums,
+                               (RowW<float> *)(w + P.L.rows_off));
     }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_THREADS), 0, s, J, n_jobs, T, sums, offs, nnz_total_dev);
     if (T > 0) hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, offs);
@@ -541,12 +547,28 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
     const int64_t T = P.L.total_tiles;
     if (T == 0) return PCT_OK;
     const bool mixed = jobs[0].precision == PCT_MIXED;
-    if (store) {
-        if (mixed) hipLaunchKernelGGL((k_emit<double, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, status);
-        else hipLaunchKernelGGL((k_emit<float, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, status);
+    void *rows = w + P.L.rows_off;
+    const dim3 grid((unsigned)T), block(TILE);
+    if (mixed) {
+        RowW<double> *rb = (RowW<double> *)rows;
+        if (!store) hipLaunchKernelGGL((k_count<double, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, rb);
+        if (store) {
+            hipLaunchKernelGGL((k_emit_wave<double, true>), grid, block, 0, s, J, n_jobs, rb, status);
+            hipLaunchKernelGGL((k_emit_lane<double, true>), grid, block, 0, s, J, n_jobs, rb, status);
+        } else {
+            hipLaunchKernelGGL((k_emit_wave<double, false>), grid, block, 0, s, J, n_jobs, rb, status);
+            hipLaunchKernelGGL((k_emit_lane<double, false>), grid, block, 0, s, J, n_jobs, rb, status);
+        }
     } else {
-        if (mixed) hipLaunchKernelGGL((k_emit<double, false>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, status);
-        else hipLaunchKernelGGL((k_emit<float, false>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, status);
+        RowW<float> *rb = (RowW<float> *)rows;
+        if (!store) hipLaunchKernelGGL((k_count<float, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, rb);
+        if (store) {
+            hipLaunchKernelGGL((k_emit_wave<float, true>), grid, block, 0, s, J, n_jobs, rb, status);
+            hipLaunchKernelGGL((k_emit_lane<float, true>), grid, block, 0, s, J, n_jobs, rb, status);
+        } else {
+            hipLaunchKernelGGL((k_emit_wave<float, false>), grid, block, 0, s, J, n_jobs, rb, status);
+            hipLaunchKernelGGL((k_emit_lane<float, false>), grid, block, 0, s, J, n_jobs, rb, status);
+        }
     }
     return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
 }

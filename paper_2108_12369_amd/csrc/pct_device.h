@@ -18,7 +18,14 @@
 
 #include <type_traits>
 
+#include "../../include/pct.h"
+
 namespace pct {
+
+// First error wins: the status word keeps the first non-OK code written to it.
+__device__ __forceinline__ void set_status_dev(int32_t *status, int32_t code) {
+    atomicCAS(status, PCT_OK, code);
+}
 
 // --------------------------------------------------------------- job descriptor
 // Flattened, device-resident form of one pct_job (host fills it, a kernel stores it
@@ -202,8 +209,10 @@ struct CountSink {
     int32_t last = -1;
 };
 
-// Emit sink: pending entry held until the next distinct voxel so that joints merge,
-// FP32 length stored as FP32 or FP16 at [pos, end), WEPL accumulated in TW.
+// Emit sink: the pending entry is held until the next distinct voxel so that joints
+// merge; its x value is fetched when the entry opens and consumed when it closes, so
+// the gather latency overlaps the walk.  Lengths are FP32, stored as FP32 or FP16 at
+// [pos, end); the WEPL is accumulated in TW.
 template <typename R, typename TW>
 struct EmitSink {
     int32_t *cols;
@@ -211,23 +220,23 @@ struct EmitSink {
     const float *x;
     int64_t pos, end;
     int32_t pcol = -1;
-    R plen = R(0);
+    float plen = 0.0f;
+    float px = 0.0f;
     TW wepl = TW(0);
     bool store, half, want_b;
 
     __device__ __forceinline__ void flush() {
         if (pcol >= 0) {
-            const float lf = (float)plen;
-            if (want_b) wepl += (TW)lf * (TW)x[pcol];
+            if (want_b) wepl += (TW)plen * (TW)px;
             if (store && pos < end) {
                 cols[pos] = pcol;
-                if (half) ((__half *)vals)[pos] = __float2half_rn(lf);
-                else ((float *)vals)[pos] = lf;
+                if (half) ((__half *)vals)[pos] = __float2half_rn(plen);
+                else ((float *)vals)[pos] = plen;
             }
             ++pos;
         }
     }
-    __device__ __forceinline__ void put(bool first, int32_t col, R len) {
+    __device__ __forceinline__ void put(bool first, int32_t col, float len) {
         if (first && col == pcol) {
             plen += len;
             return;
@@ -235,8 +244,12 @@ struct EmitSink {
         flush();
         pcol = col;
         plen = len;
+        if (want_b) px = x[col];
     }
 };
+
+template <class S> struct is_count : std::false_type {};
+template <> struct is_count<CountSink> : std::true_type {};
 
 // ------------------------------------------------------------------ the traversal
 // Clip A + l D, l in [lo, hi], to the grid box (slab test).  False if it misses.
@@ -256,7 +269,9 @@ __device__ __forceinline__ bool clip_box(const JobDev &J, const R A[3], const R 
     return lo < hi;
 }
 
-// Walk from P (parameter lo) to E (parameter hi) along A + l D; i = voxel of P.
+// Walk from P (parameter lo) to E (parameter hi) along A + l D.  The step count per
+// axis is fixed by the voxel indices of P and E; the order of the face crossings is
+// decided by their parameters l = (face - A_d) / D_d (one reciprocal per axis).
 template <typename R, int DIM, class S>
 __device__ __forceinline__ void walk(const JobDev &J, const R A[3], const R D[3], R lo, R hi,
                                      const R P[3], const R E[3], S &s) {
@@ -268,7 +283,7 @@ __device__ __forceinline__ void walk(const JobDev &J, const R A[3], const R D[3]
         bud[d] = abs(e[d] - i[d]);
         st[d] = e[d] > i[d] ? 1 : -1;
     }
-    if constexpr (std::is_same<S, CountSink>::value) {
+    if constexpr (is_count<S>::value) {
         int64_t c = 1;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) c += bud[d];
@@ -277,8 +292,12 @@ __device__ __forceinline__ void walk(const JobDev &J, const R A[3], const R D[3]
         s.last = col_of<DIM>(J, e);
     } else {
         R dn2 = R(0);
+        R inv[3] = {R(0), R(0), R(0)};
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) dn2 += D[d] * D[d];
+        for (int d = 0; d < DIM; ++d) {
+            dn2 += D[d] * D[d];
+            inv[d] = (bud[d] > 0 && D[d] != R(0)) ? R(1) / D[d] : R(0);
+        }
         const R Dn = r_sqrt<R>(dn2);
         R lp = lo;
         bool first = true;
@@ -289,7 +308,7 @@ __device__ __forceinline__ void walk(const JobDev &J, const R A[3], const R D[3]
             for (int d = 0; d < DIM; ++d) {
                 if (bud[d] > 0) {
                     const R plane = R(J.o[d]) + R(i[d] + (st[d] > 0 ? 1 : 0)) * R(J.h[d]);
-                    const R ld = (D[d] != R(0)) ? (plane - A[d]) / D[d] : r_inf<R>();
+                    const R ld = (D[d] != R(0)) ? (plane - A[d]) * inv[d] : r_inf<R>();
                     if (a < 0 || ld < la) {
                         a = d;
                         la = ld;
@@ -299,15 +318,14 @@ __device__ __forceinline__ void walk(const JobDev &J, const R A[3], const R D[3]
             if (a < 0) break;
             R lc = la > lp ? la : lp;
             lc = lc < hi ? lc : hi;
-            s.put(first, col_of<DIM>(J, i), (lc - lp) * Dn);
+            s.put(first, col_of<DIM>(J, i), (float)((lc - lp) * Dn));
             first = false;
             lp = lc;
-            // (a is < DIM; written as a select chain so that i stays in registers)
             if (a == 0) { i[0] += st[0]; bud[0] -= 1; }
             else if (a == 1) { i[1] += st[1]; bud[1] -= 1; }
             else { i[2] += st[2]; bud[2] -= 1; }
         }
-        s.put(first, col_of<DIM>(J, i), (hi - lp) * Dn);
+        s.put(first, col_of<DIM>(J, i), (float)((hi - lp) * Dn));
     }
 }
 
@@ -327,31 +345,143 @@ __device__ __forceinline__ void segment(const JobDev &J, const R A[3], const R D
     walk<R, DIM>(J, A, D, lo, hi, P, E, s);
 }
 
+// Position of the previous spline sample and its voxel, carried from chord to chord.
+template <typename R>
+struct ChordState {
+    R A[3];
+    R fa[3];       // unclamped floor((A - o) / h) per axis
+    bool a_in;     // A lies in the grid box
+    int32_t ca;    // column of A's voxel (when a_in)
+};
+
 template <typename R, int DIM>
-__device__ __forceinline__ bool inside_box(const JobDev &J, const R p[3]) {
-    bool ok = true;
+__device__ __forceinline__ void chord_start(const JobDev &J, const R P0[3], ChordState<R> &c) {
+    c.a_in = true;
+    int i[3] = {0, 0, 0};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        const R f = vox_floor<R>(p[d], J.o[d], J.invh[d]);
-        ok = ok && (f >= R(0)) && (f <= R(J.n[d] - 1));
+    for (int d = 0; d < 3; ++d) {
+        c.A[d] = P0[d];
+        c.fa[d] = R(0);
+        if (d < DIM) {
+            c.fa[d] = vox_floor<R>(P0[d], J.o[d], J.invh[d]);
+            c.a_in = c.a_in && (c.fa[d] >= R(0)) && (c.fa[d] <= R(J.n[d] - 1));
+            i[d] = (int)c.fa[d];
+        }
     }
-    return ok;
+    c.ca = c.a_in ? col_of<DIM>(J, i) : -1;
 }
 
-// Chord between two consecutive spline samples.  When both ends lie in the box the
-// clip cannot move them, so the walk starts directly.
+// Chord from the carried sample A to the new sample B.  When both lie in the box no
+// clipping can move them: the walk starts at A's voxel and takes |i_d(B) - i_d(A)|
+// steps per axis, ordered by comparing the crossing parameters cross-multiplied in R
+// (no division); the lengths of the pieces are formed in FP32.
 template <typename R, int DIM, class S>
-__device__ __forceinline__ void chord(const JobDev &J, const R A[3], const R B[3], S &s) {
-    R D[3] = {R(0), R(0), R(0)};
+__device__ __forceinline__ void chord_to(const JobDev &J, ChordState<R> &c, const R B[3], S &s) {
+    R fb[3] = {R(0), R(0), R(0)};
+    bool b_in = true;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) D[d] = B[d] - A[d];
-    if (inside_box<R, DIM>(J, A) && inside_box<R, DIM>(J, B)) walk<R, DIM>(J, A, D, R(0), R(1), A, B, s);
-    else segment<R, DIM>(J, A, D, R(0), R(1), B, s);
+    for (int d = 0; d < DIM; ++d) {
+        fb[d] = vox_floor<R>(B[d], J.o[d], J.invh[d]);
+        b_in = b_in && (fb[d] >= R(0)) && (fb[d] <= R(J.n[d] - 1));
+    }
+    int ib[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ib[d] = (int)fb[d];
+    const int32_t cb = b_in ? col_of<DIM>(J, ib) : -1;
+    if (c.a_in && b_in) {
+        int ia[3] = {0, 0, 0}, bud[3] = {0, 0, 0}, st[3] = {0, 0, 0};
+        int tot = 0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            ia[d] = (int)c.fa[d];
+            bud[d] = abs(ib[d] - ia[d]);
+            st[d] = ib[d] > ia[d] ? 1 : -1;
+            tot += bud[d];
+        }
+        if constexpr (is_count<S>::value) {
+            s.n += tot + (c.ca != s.last ? 1 : 0);
+            s.last = cb;
+        } else {
+            R D[3] = {R(0), R(0), R(0)};
+            float Df[3] = {0.f, 0.f, 0.f};
+            float dn2 = 0.f;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                D[d] = B[d] - c.A[d];
+                Df[d] = (float)D[d];
+                dn2 = fmaf(Df[d], Df[d], dn2);
+            }
+            const float len = __builtin_amdgcn_sqrtf(dn2);
+            if (tot == 0) {
+                s.put(true, c.ca, len);
+            } else {
+                float lp = 0.f;
+                bool first = true;
+                int32_t ci = c.ca;
+                while (tot > 0) {
+                    // axis of the nearest crossing: l_d = |face_d - A_d| / |D_d|
+                    int a = -1;
+                    R na = R(0), da = R(1);
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) {
+                        if (bud[d] > 0) {
+                            const R plane = R(J.o[d]) + R(ia[d] + (st[d] > 0 ? 1 : 0)) * R(J.h[d]);
+                            const R nd = plane - c.A[d];
+                            const R ad = D[d] < R(0) ? -D[d] : D[d];
+                            const R an = nd < R(0) ? -nd : nd;
+                            if (a < 0 || an * da < na * ad) {
+                                a = d;
+                                na = an;
+                                da = ad;
+                            }
+                        }
+                    }
+                    float lc = (float)na * __builtin_amdgcn_rcpf((float)da);
+                    lc = lc > lp ? lc : lp;
+                    lc = lc < 1.f ? lc : 1.f;
+                    s.put(first, ci, (lc - lp) * len);
+                    first = false;
+                    lp = lc;
+                    if (a == 0) { ia[0] += st[0]; bud[0] -= 1; }
+                    else if (a == 1) { ia[1] += st[1]; bud[1] -= 1; }
+                    else { ia[2] += st[2]; bud[2] -= 1; }
+                    --tot;
+                    ci = col_of<DIM>(J, ia);
+                }
+                s.put(first, ci, (1.f - lp) * len);
+            }
+        }
+    } else {
+        R D[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) D[d] = B[d] - c.A[d];
+        segment<R, DIM>(J, c.A, D, R(0), R(1), B, s);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c.A[d] = B[d];
+        c.fa[d] = fb[d];
+    }
+    c.a_in = b_in;
+    c.ca = cb;
 }
 
 // ------------------------------------------------------------------------ one row
-template <typename R, int DIM, bool CURVED, class S>
-__device__ void trace_row(const JobDev &J, int64_t g, S &s) {
+// Geometry of proton g's path [Sec. II-B]: a straight line (Q, u) or, for a spline path
+// that meets the outer boundary, entry P0 with direction d0, exit P1 with direction d1
+// and the power basis c1..c3 of the cubic Hermite curve (origin P0), N chords.
+template <typename R>
+struct PathGeom {
+    bool curved;
+    R Q[3], u[3];
+    R P0[3], d0[3], P1[3], d1[3];
+    R c1[3], c2[3], c3[3];
+    R L, invN;
+    int32_t N;
+};
+
+template <typename R, int DIM, bool CURVED>
+__device__ __forceinline__ void make_path(const JobDev &J, int64_t g, PathGeom<R> &p) {
     const int32_t k = (int32_t)(((g + 1) * (int64_t)J.K - 1) / J.P);
     R c, sn;
     beam_angle<R>(J, k, c, sn);
@@ -361,13 +491,14 @@ __device__ void trace_row(const JobDev &J, int64_t g, S &s) {
     draw2(J.seed, 0, (uint64_t)g, 0, w0, w1);
     const R t = R(J.t_lo) + R(J.t_span) * unit_uniform<R>(w0);
     const R v = (DIM == 3) ? R(J.v_lo) + R(J.v_span) * unit_uniform<R>(w1) : R(0);
-    const R Q[3] = {t * th[0], t * th[1], v};
-    const R ninf = -r_inf<R>(), pinf = r_inf<R>();
-
-    if constexpr (!CURVED) {
-        segment<R, DIM>(J, Q, u, ninf, pinf, (const R *)nullptr, s);
-        return;
-    } else {
+    p.Q[0] = t * th[0];
+    p.Q[1] = t * th[1];
+    p.Q[2] = v;
+    p.u[0] = u[0];
+    p.u[1] = u[1];
+    p.u[2] = u[2];
+    p.curved = false;
+    if constexpr (CURVED) {
         R zt, zv;
         normal_pair<R>(J.seed, 1, (uint64_t)g, zt, zv);
         const R tti = r_tan<R>(R(J.sig_in) * zt);
@@ -375,15 +506,19 @@ __device__ void trace_row(const JobDev &J, int64_t g, S &s) {
         R d0[3] = {u[0] + tti * th[0], u[1] + tti * th[1], tvi};
         normalize3<R>(d0);
         R l1, l2;
-        if (!boundary_hit<R, DIM>(J, Q, d0, l1, l2)) {
-            segment<R, DIM>(J, Q, d0, ninf, pinf, (const R *)nullptr, s);
+        if (!boundary_hit<R, DIM>(J, p.Q, d0, l1, l2)) {
+            // misses the phantom: straight along the entry direction
+            p.u[0] = d0[0];
+            p.u[1] = d0[1];
+            p.u[2] = d0[2];
             return;
         }
+        p.curved = true;
         R P0[3], P1[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            P0[i] = Q[i] + l1 * d0[i];
-            P1[i] = Q[i] + l2 * d0[i];
+            P0[i] = p.Q[i] + l1 * d0[i];
+            P1[i] = p.Q[i] + l2 * d0[i];
         }
         R z1, z2;
         normal_pair<R>(J.seed, 2, (uint64_t)g, z1, z2);
@@ -409,7 +544,7 @@ __device__ void trace_row(const JobDev &J, int64_t g, S &s) {
         }
         R Qd[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) Qd[i] = Q[i] + lat_t * nt[i] + lat_v * nv[i];
+        for (int i = 0; i < 3; ++i) Qd[i] = p.Q[i] + lat_t * nt[i] + lat_v * nv[i];
         R m1, m2;
         if (boundary_hit<R, DIM>(J, Qd, d0, m1, m2)) {
 #pragma unroll
@@ -427,38 +562,49 @@ __device__ void trace_row(const JobDev &J, int64_t g, S &s) {
         const R L = r_sqrt<R>(dP[0] * dP[0] + dP[1] * dP[1] + dP[2] * dP[2]);
         const R steps = L / R(J.step);
         int32_t N = (int32_t)r_ceil<R>(steps);
-        N = N < 1 ? 1 : N;
-        // power basis of the cubic Hermite curve with tangents L d0 and L d1
-        R c1[3], c2[3], c3[3];
+        p.N = N < 1 ? 1 : N;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            c1[i] = L * d0[i];
-            c2[i] = R(3) * dP[i] - R(2) * L * d0[i] - L * d1[i];
-            c3[i] = R(-2) * dP[i] + L * d0[i] + L * d1[i];
+            p.P0[i] = P0[i];
+            p.P1[i] = P1[i];
+            p.d0[i] = d0[i];
+            p.d1[i] = d1[i];
+            p.c1[i] = L * d0[i];
+            p.c2[i] = R(3) * dP[i] - R(2) * L * d0[i] - L * d1[i];
+            p.c3[i] = R(-2) * dP[i] + L * d0[i] + L * d1[i];
         }
-        const R invN = R(1) / R(N);
-
-        segment<R, DIM>(J, P0, d0, ninf, R(0), (const R *)nullptr, s);
-        R A[3] = {P0[0], P0[1], P0[2]};
-        for (int32_t j = 1; j <= N; ++j) {
-            R B[3];
-            if (j == N) {
-                B[0] = P1[0];
-                B[1] = P1[1];
-                B[2] = P1[2];
-            } else {
-                const R sj = R(j) * invN;
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    B[i] = r_fma<R>(r_fma<R>(r_fma<R>(c3[i], sj, c2[i]), sj, c1[i]), sj, P0[i]);
-            }
-            chord<R, DIM>(J, A, B, s);
-            A[0] = B[0];
-            A[1] = B[1];
-            A[2] = B[2];
-        }
-        segment<R, DIM>(J, P1, d1, R(0), pinf, (const R *)nullptr, s);
+        p.L = L;
+        p.invN = R(1) / R(p.N);
     }
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ void spline_point(const PathGeom<R> &p, int32_t j, R B[3]) {
+    const R sj = R(j) * p.invN;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        B[i] = (i < DIM) ? r_fma<R>(r_fma<R>(r_fma<R>(p.c3[i], sj, p.c2[i]), sj, p.c1[i]), sj, p.P0[i]) : R(0);
+}
+
+template <typename R, int DIM, bool CURVED, class S>
+__device__ __forceinline__ void trace_row(const JobDev &J, int64_t g, S &s) {
+    PathGeom<R> p;
+    make_path<R, DIM, CURVED>(J, g, p);
+    const R ninf = -r_inf<R>(), pinf = r_inf<R>();
+    if (!p.curved) {
+        segment<R, DIM>(J, p.Q, p.u, ninf, pinf, (const R *)nullptr, s);
+        return;
+    }
+    segment<R, DIM>(J, p.P0, p.d0, ninf, R(0), (const R *)nullptr, s);
+    ChordState<R> cs;
+    chord_start<R, DIM>(J, p.P0, cs);
+    for (int32_t j = 1; j < p.N; ++j) {
+        R B[3];
+        spline_point<R, DIM>(p, j, B);
+        chord_to<R, DIM>(J, cs, B, s);
+    }
+    chord_to<R, DIM>(J, cs, p.P1, s);
+    segment<R, DIM>(J, p.P1, p.d1, R(0), pinf, (const R *)nullptr, s);
 }
 
 template <typename R, class S>
