@@ -28,21 +28,6 @@ namespace pct {
 constexpr int WAVE = 64;
 constexpr int BATCH = 16;   // rows prepared per wave at a time (one per lane)
 
-// Per-row description of the path, written by the count pass (one lane per row) into
-// the workspace and read by the emit pass with uniform (scalar) loads.
-template <typename R>
-struct RowW {
-    int32_t kind;       // 0: no entry, 1: one ray, 2: ray + spline + ray, 3: per-lane walk
-    int32_t N;          // spline chords
-    R A0[3], D0[3];     // first ray: points A0 + l D0, l in [lo0, hi0]
-    R lo0, hi0;
-    R A1[3], D1[3];     // last ray (kind 2)
-    R lo1, hi1;
-    R c1[3], c2[3], c3[3];   // spline power basis, origin A0 (= entry point)
-    R invN;
-    double bfac;        // WEPL noise factor 1 + r z
-};
-
 // A straight ray prepared for the cell walk (uniform over the wave).
 template <typename R>
 struct RayW {
@@ -53,6 +38,20 @@ struct RayW {
     // the dominant axis's values, kept apart so that no array is indexed at run time
     R a_dom, inv_dom, o_dom, h_dom;
     int is_dom;
+};
+
+// Per-row description of the path, written by the count pass (one lane per row) into
+// the workspace and read by the emit pass with uniform (scalar) loads: the prepared
+// rays (the whole straight path, or the rays before the entry and after the exit) and
+// the spline's power basis.
+template <typename R>
+struct RowW {
+    int32_t kind;       // 0: no entry, 1: one ray, 2: ray + spline + ray, 3: per-lane walk
+    int32_t N;          // spline chords
+    RayW<R> ray[2];     // ray[0].A is the entry point P0, ray[1].A the exit point P1 (kind 2)
+    R c1[3], c2[3], c3[3];   // spline power basis, origin P0
+    R invN;
+    double bfac;        // WEPL noise factor 1 + r z
 };
 
 template <typename R, int DIM>
@@ -97,7 +96,7 @@ __device__ __forceinline__ void ray_prepare(const JobDev &J, const R A[3], const
         }
     }
     r.sdom = dd >= 0 ? 1 : -1;
-    r.ncell = abs(dd) + 1;
+    r.ncell = (lo < hi) ? abs(dd) + 1 : 0;   // no cell when the ray misses the box
 }
 
 // Parameter of the dominant-axis face between cell m-1 and cell m (1 <= m < ncell).
@@ -151,15 +150,46 @@ __device__ __forceinline__ T shfl_up_t(T v, int off) {
     return __shfl_up(v, (unsigned)off, WAVE);
 }
 
+// Inclusive add-scan over the wavefront with DPP: shifts by 1, 2, 4, 8 inside each row
+// of 16 lanes, then the last lane of row 0 / rows 0-1 is added to the rows after it.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 __device__ __forceinline__ int wave_excl_scan(int v, int lane, int &total) {
-    int s = v;
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        const int t = __shfl_up(s, (unsigned)off, WAVE);
-        if (lane >= off) s += t;
-    }
-    total = __shfl(s, WAVE - 1, WAVE);
+    (void)lane;
+    const int s = wave_incl_scan(v);
+    total = __builtin_amdgcn_readlane(s, WAVE - 1);
     return s - v;
+}
+
+// One step of the segmented scan: a lane without a reset so far takes the value of the
+// lane `ctrl` selects and adds it.
+template <int CTRL, int ROWMASK, bool BOUND>
+__device__ __forceinline__ void seg_step(float &v, int &f) {
+    const float vo = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                           ROWMASK, 0xf, BOUND));
+    const int fo = __builtin_amdgcn_update_dpp(0, f, CTRL, ROWMASK, 0xf, BOUND);
+    if (!f) {
+        v += vo;
+        f = fo;
+    }
+}
+
+// Inclusive segmented sum: value restarts at lanes with f set.
+__device__ __forceinline__ void wave_seg_scan(float &v, int &f) {
+    seg_step<0x111, 0xf, true>(v, f);
+    seg_step<0x112, 0xf, true>(v, f);
+    seg_step<0x114, 0xf, true>(v, f);
+    seg_step<0x118, 0xf, true>(v, f);
+    seg_step<0x142, 0xa, false>(v, f);
+    seg_step<0x143, 0xc, false>(v, f);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -206,18 +236,18 @@ template <typename R, int DIM>
 __device__ __forceinline__ void spline_at(const RowW<R> &w, int j, R out[3]) {
     if (j == 0) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) out[d] = w.A0[d];
+        for (int d = 0; d < 3; ++d) out[d] = w.ray[0].A[d];
         return;
     }
     if (j == w.N) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) out[d] = w.A1[d];
+        for (int d = 0; d < 3; ++d) out[d] = w.ray[1].A[d];
         return;
     }
     const R s = R(j) * w.invN;
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-        out[d] = (d < DIM) ? r_fma<R>(r_fma<R>(r_fma<R>(w.c3[d], s, w.c2[d]), s, w.c1[d]), s, w.A0[d]) : R(0);
+        out[d] = (d < DIM) ? r_fma<R>(r_fma<R>(r_fma<R>(w.c3[d], s, w.c2[d]), s, w.c1[d]), s, w.ray[0].A[d]) : R(0);
 }
 
 // Voxel of a spline sample.  The row's control-point hull lies in the box, so the floor
@@ -476,6 +506,76 @@ __device__ __forceinline__ void cell_fast(const JobDev &J, const RayW<R> &r, con
     wk.pend = (tot == 0 ? wk.pend : 0.f) + (float)((le - lp) * r.Dn);
 }
 
+// Chord between two spline samples given by voxel index and in-voxel position (voxel
+// units, R), at most one crossing per axis.  The displacement and the distance to the
+// face are formed in R (no cancellation for a chord nearly parallel to a face), their
+// ratio -- the crossing parameter -- and the piece lengths in FP32.
+template <typename R, int DIM, class F>
+__device__ __forceinline__ void chord_frac(const JobDev &J, const int Ip[3], const R fp[3], const int Ie[3],
+                                           const R fe[3], Walker<R> &wk, F &&close) {
+    float lam[3], dn2 = 0.f;
+    int32_t dcol[3];
+    int tot = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lam[d] = 2.f;
+        dcol[d] = 0;
+        if (d < DIM) {
+            const int di = Ie[d] - Ip[d];
+            const R df = (di > 0 ? R(1) : (di < 0 ? R(-1) : R(0))) + (fe[d] - fp[d]);   // voxel units
+            const float dff = (float)df;
+            const float dm = dff * (float)J.h[d];                   // mm
+            dn2 = fmaf(dm, dm, dn2);
+            const bool up = di > 0;
+            tot += di != 0 ? 1 : 0;
+            const float dist = (float)(up ? R(1) - fp[d] : fp[d]);
+            lam[d] = di != 0 ? dist * __builtin_amdgcn_rcpf(fabsf(dff)) : 2.f;
+            dcol[d] = (up ? 1 : -1) * col_stride<DIM>(J, d);
+        }
+    }
+    const float len = __builtin_amdgcn_sqrtf(dn2);
+    // order the (at most DIM) crossings; ties keep the lower axis
+#define PCT_CSWAP(a, b)                                                  \
+    if (lam[b] < lam[a]) {                                               \
+        const float tl = lam[a]; lam[a] = lam[b]; lam[b] = tl;           \
+        const int32_t tc = dcol[a]; dcol[a] = dcol[b]; dcol[b] = tc;     \
+    }
+    PCT_CSWAP(0, 1)
+    if (DIM == 3) {
+        PCT_CSWAP(1, 2)
+        PCT_CSWAP(0, 1)
+    }
+#undef PCT_CSWAP
+    float lp = 0.f;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const bool go = k < tot;
+        float lc = lam[k] > lp ? lam[k] : lp;
+        lc = lc < 1.f ? lc : 1.f;
+        close(go, wk.cur, (k == 0 ? wk.pend : 0.f) + (lc - lp) * len);
+        wk.cur += go ? dcol[k] : 0;
+        lp = go ? lc : lp;
+    }
+    wk.pend = (tot == 0 ? wk.pend : 0.f) + (1.f - lp) * len;
+}
+
+// Voxel index and in-voxel position (voxel units) of a spline sample.
+template <typename R, int DIM>
+__device__ __forceinline__ void sample_vox(const JobDev &J, const R p[3], int I[3], R fr[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        I[d] = 0;
+        fr[d] = R(0);
+        if (d < DIM) {
+            const R f = (p[d] - R(J.o[d])) * R(J.invh[d]);
+            int v = (int)r_floor<R>(f);
+            v = v < 0 ? 0 : (v > J.n[d] - 1 ? J.n[d] - 1 : v);
+            I[d] = v;
+            fr[d] = f - R(v);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ uniform values
 __device__ __forceinline__ double uni(double v) {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
@@ -526,176 +626,197 @@ template <typename TW, typename R>
 __device__ __forceinline__ void stitch(RowOut<TW> &out, RowCarry &rc, const Walker<R> &wk, int c, int P, int ctot,
                                        int32_t col_start, int lane, int last_lane) {
     const bool f = c > 0;
-    bool fs = f;
+    int fs = f ? 1 : 0;
     float vs = wk.pend;
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        const float vo = __shfl_up(vs, (unsigned)off, WAVE);
-        const int fo = __shfl_up((int)fs, (unsigned)off, WAVE);
-        if (lane >= off && !fs) {
-            vs += vo;
-            fs = fo != 0;
-        }
-    }
+    wave_seg_scan(vs, fs);
     const float Oend = fs ? vs : rc.O + vs;   // open length after this lane
     float Oin = __shfl_up(Oend, 1u, WAVE);    // ... before it
     if (lane == 0) Oin = rc.O;
     if (f) out.put((int32_t)rc.C + P, col_start, Oin + wk.head);
     out.fold();
-    rc.O = __shfl(Oend, last_lane, WAVE);
-    rc.open_col = __shfl(wk.cur, last_lane, WAVE);
+    rc.O = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Oend), last_lane));
+    rc.open_col = __builtin_amdgcn_readlane(wk.cur, last_lane);
     rc.C += ctot;
     rc.any = true;
 }
 
-// Cells of one straight ray (uniform RayW), K consecutive cells per lane.
-template <typename R, int DIM, int K, typename TW>
+// Cells of one straight ray (uniform RayW), ceil(ncell / 64) consecutive cells per lane:
+// a whole ray is one block.  The second pass recomputes the cells (cheap).
+template <typename R, int DIM, typename TW>
 __device__ __forceinline__ void walk_cells(const JobDev &J, const RayW<R> &r, RowOut<TW> &out, RowCarry &rc,
                                            int lane) {
     const int n = r.ncell;
-    for (int base = 0; base < n; base += WAVE * K) {
-        const int first = base + lane * K;
-        int Is[3] = {0, 0, 0};
-        R ls = R(0);
-        if (first < n) {
-            ls = ray_lam<R>(J, r, first);
-            ray_index<R, DIM>(J, r, first, ls, Is);
-        }
-        int Ie[K][3];
-        R le[K];
-        int c = 0;
-        {
-            int Ip[3] = {Is[0], Is[1], Is[2]};
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int m = first + k;
-                if (m < n) {
-                    le[k] = ray_lam<R>(J, r, m + 1);
-                    ray_index<R, DIM>(J, r, m + 1, le[k], Ie[k]);
-#pragma unroll
-                    for (int d = 0; d < DIM; ++d) c += abs(Ie[k][d] - Ip[d]);
-                } else {
-                    le[k] = ls;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) Ie[k][d] = Ip[d];
-                }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) Ip[d] = Ie[k][d];
-            }
-        }
-        int ctot;
-        const int P = wave_excl_scan(c, lane, ctot);
-        const int32_t col_start = col_of<DIM>(J, Is);
-        Walker<R> wk;
-        wk.head = 0.f;
-        wk.pend = 0.f;
-        wk.done = 0;
-        wk.cur = col_start;
-        const int32_t rel0 = (int32_t)rc.C + P;
-        auto close = [&](bool ok, int32_t col, float len) {
-            if (ok) {
-                if (wk.done == 0) wk.head = len;
-                else out.put(rel0 + wk.done, col, len);
-                ++wk.done;
-            }
-        };
-        {
-            int Ip[3] = {Is[0], Is[1], Is[2]};
-            R lp = ls;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (first + k < n) {
-                    bool one = true;
-#pragma unroll
-                    for (int d = 0; d < DIM; ++d) one = one && abs(Ie[k][d] - Ip[d]) <= 1;
-                    if (one) cell_fast<R, DIM>(J, r, Ip, lp, Ie[k], le[k], wk, close);
-                    else cell_pieces<R, DIM>(J, r, Ip, lp, Ie[k], le[k], wk, close);
-                }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) Ip[d] = Ie[k][d];
-                lp = le[k];
-            }
-        }
-        const int last = ((n < base + WAVE * K) ? n : base + WAVE * K) - 1 - base;
-        stitch(out, rc, wk, c, P, ctot, col_start, lane, last / K);
+    if (n == 0) return;
+    const int Kr = (n + WAVE - 1) / WAVE;
+    const int first = lane * Kr;
+    const int lastc = (first + Kr < n) ? first + Kr : n;   // this lane's cells [first, lastc)
+    int Is[3] = {0, 0, 0};
+    R ls = R(0);
+    if (first < n) {
+        ls = ray_lam<R>(J, r, first);
+        ray_index<R, DIM>(J, r, first, ls, Is);
     }
+    // the voxel indices at the cell boundaries are monotone along a ray (clamped that
+    // way), so the crossings of the lane's cells are the index differences of its ends
+    int c = 0;
+    if (first < n) {
+        int Ie[3];
+        const R le = ray_lam<R>(J, r, lastc);
+        ray_index<R, DIM>(J, r, lastc, le, Ie);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) c += abs(Ie[d] - Is[d]);
+    }
+    int ctot;
+    const int P = wave_excl_scan(c, lane, ctot);
+    const int32_t col_start = col_of<DIM>(J, Is);
+    Walker<R> wk;
+    wk.head = 0.f;
+    wk.pend = 0.f;
+    wk.done = 0;
+    wk.cur = col_start;
+    const int32_t rel0 = (int32_t)rc.C + P;
+    auto close = [&](bool ok, int32_t col, float len) {
+        if (ok) {
+            if (wk.done == 0) wk.head = len;
+            else out.put(rel0 + wk.done, col, len);
+            ++wk.done;
+        }
+    };
+    {
+        int Ip[3] = {Is[0], Is[1], Is[2]};
+        R lp = ls;
+        for (int m = first; m < lastc; ++m) {
+            int Ie[3];
+            const R le = ray_lam<R>(J, r, m + 1);
+            ray_index<R, DIM>(J, r, m + 1, le, Ie);
+            bool one = true;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) one = one && abs(Ie[d] - Ip[d]) <= 1;
+            if (one) cell_fast<R, DIM>(J, r, Ip, lp, Ie, le, wk, close);
+            else cell_pieces<R, DIM>(J, r, Ip, lp, Ie, le, wk, close);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Ip[d] = Ie[d];
+            lp = le;
+        }
+    }
+    stitch(out, rc, wk, c, P, ctot, col_start, lane, (n - 1) / Kr);
 }
 
-// Chords of the spline (N of them, samples 0..N), K consecutive chords per lane.
-template <typename R, int DIM, int K, typename TW>
+// True when every coordinate of the spline is strictly monotone over [s0, s1], with a
+// rate that moves each chord by far more than the rounding of a sample: then the voxel
+// indices of the computed samples are monotone too, and the crossings between samples
+// j0 and j1 add up to the index differences of the two.  x'(s) = c1 + 2 c2 s + 3 c3 s^2.
+template <typename R, int DIM>
+__device__ __forceinline__ bool spline_monotone(const RowW<R> &w, R s0, R s1) {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const R a = w.c1[d], b = R(2) * w.c2[d], c3 = R(3) * w.c3[d];
+        const R g0 = r_fma<R>(r_fma<R>(c3, s0, b), s0, a);
+        const R g1 = r_fma<R>(r_fma<R>(c3, s1, b), s1, a);
+        R gmin = (g0 < R(0) ? -g0 : g0);
+        const R ag1 = (g1 < R(0) ? -g1 : g1);
+        gmin = ag1 < gmin ? ag1 : gmin;
+        bool same = (g0 > R(0)) == (g1 > R(0));
+        // the vertex of the derivative parabola
+        if (c3 != R(0)) {
+            const R sv = -b / (R(2) * c3);
+            if (sv > s0 && sv < s1) {
+                const R gv = r_fma<R>(r_fma<R>(c3, sv, b), sv, a);
+                same = same && ((gv > R(0)) == (g0 > R(0)));
+                const R agv = gv < R(0) ? -gv : gv;
+                gmin = agv < gmin ? agv : gmin;
+            }
+        }
+        ok = ok && same && (gmin * w.invN > R(sizeof(R) == 8 ? 1e-9 : 1e-2));
+    }
+    return ok;
+}
+
+// Chords of the spline (N of them, samples 0..N): ceil(N / 64) consecutive chords per
+// lane, so a whole spline is one block.  The first pass reads the crossing count off the
+// lane's first and last samples when the spline is monotone there, else sample by sample;
+// the second pass walks the chords.
+template <typename R, int DIM, typename TW>
 __device__ __forceinline__ void walk_chords(const JobDev &J, const RowW<R> &w, RowOut<TW> &out, RowCarry &rc,
                                             int lane) {
     const int n = w.N;
-    for (int base = 0; base < n; base += WAVE * K) {
-        const int first = base + lane * K;
-        int Is[3] = {0, 0, 0};
-        R Ps[3] = {R(0), R(0), R(0)};
-        if (first < n) {
-            spline_at<R, DIM>(w, first, Ps);
-            spline_index<R, DIM>(J, Ps, Is);
-        }
-        int Ie[K][3];
-        R Pe[K][3];
-        int c = 0;
-        {
+    const int K = (n + WAVE - 1) / WAVE;
+    const int first = lane * K;
+    const int lastc = (first + K < n) ? first + K : n;
+    int Is[3] = {0, 0, 0};
+    R fs[3] = {R(0), R(0), R(0)};
+    int c = 0;
+    if (first < n) {
+        R Ps[3], Pe[3];
+        spline_at<R, DIM>(w, first, Ps);
+        sample_vox<R, DIM>(J, Ps, Is, fs);
+        const R s0 = R(first) * w.invN, s1 = R(lastc) * w.invN;
+        if (spline_monotone<R, DIM>(w, s0, s1)) {
+            int Ie[3];
+            R fe[3];
+            spline_at<R, DIM>(w, lastc, Pe);
+            sample_vox<R, DIM>(J, Pe, Ie, fe);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) c += abs(Ie[d] - Is[d]);
+        } else {
             int Ip[3] = {Is[0], Is[1], Is[2]};
+            for (int j = first + 1; j <= lastc; ++j) {
+                int Ie[3];
+                R fe[3];
+                spline_at<R, DIM>(w, j, Pe);
+                sample_vox<R, DIM>(J, Pe, Ie, fe);
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int j = first + k;
-                if (j < n) {
-                    spline_at<R, DIM>(w, j + 1, Pe[k]);
-                    spline_index<R, DIM>(J, Pe[k], Ie[k]);
-#pragma unroll
-                    for (int d = 0; d < DIM; ++d) c += abs(Ie[k][d] - Ip[d]);
-                } else {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        Ie[k][d] = Ip[d];
-                        Pe[k][d] = R(0);
-                    }
-                }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) Ip[d] = Ie[k][d];
-            }
-        }
-        int ctot;
-        const int P = wave_excl_scan(c, lane, ctot);
-        const int32_t col_start = col_of<DIM>(J, Is);
-        Walker<R> wk;
-        wk.head = 0.f;
-        wk.pend = 0.f;
-        wk.done = 0;
-        wk.cur = col_start;
-        const int32_t rel0 = (int32_t)rc.C + P;
-        auto close = [&](bool ok, int32_t col, float len) {
-            if (ok) {
-                if (wk.done == 0) wk.head = len;
-                else out.put(rel0 + wk.done, col, len);
-                ++wk.done;
-            }
-        };
-        {
-            int Ip[3] = {Is[0], Is[1], Is[2]};
-            R Pp[3] = {Ps[0], Ps[1], Ps[2]};
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (first + k < n) {
-                    bool one = true;
-#pragma unroll
-                    for (int d = 0; d < DIM; ++d) one = one && abs(Ie[k][d] - Ip[d]) <= 1;
-                    if (one) chord_fast<R, DIM>(J, Ip, Pp, Ie[k], Pe[k], wk, close);
-                    else chord_pieces<R, DIM>(J, Ip, Pp, Ie[k], Pe[k], wk, close);
-                }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    Ip[d] = Ie[k][d];
-                    Pp[d] = Pe[k][d];
+                for (int d = 0; d < DIM; ++d) {
+                    c += abs(Ie[d] - Ip[d]);
+                    Ip[d] = Ie[d];
                 }
             }
         }
-        const int last = ((n < base + WAVE * K) ? n : base + WAVE * K) - 1 - base;
-        stitch(out, rc, wk, c, P, ctot, col_start, lane, last / K);
     }
+    int ctot;
+    const int P = wave_excl_scan(c, lane, ctot);
+    const int32_t col_start = col_of<DIM>(J, Is);
+    Walker<R> wk;
+    wk.head = 0.f;
+    wk.pend = 0.f;
+    wk.done = 0;
+    wk.cur = col_start;
+    const int32_t rel0 = (int32_t)rc.C + P;
+    auto close = [&](bool ok, int32_t col, float len) {
+        if (ok) {
+            if (wk.done == 0) wk.head = len;
+            else out.put(rel0 + wk.done, col, len);
+            ++wk.done;
+        }
+    };
+    {
+        int Ip[3] = {Is[0], Is[1], Is[2]};
+        R fp[3] = {fs[0], fs[1], fs[2]};
+        for (int j = first; j < lastc; ++j) {
+            R Pe[3];
+            int Ie[3];
+            R fe[3];
+            spline_at<R, DIM>(w, j + 1, Pe);
+            sample_vox<R, DIM>(J, Pe, Ie, fe);
+            bool one = true;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) one = one && abs(Ie[d] - Ip[d]) <= 1;
+            if (one) {
+                chord_frac<R, DIM>(J, Ip, fp, Ie, fe, wk, close);
+            } else {
+                R Pa[3];
+                spline_at<R, DIM>(w, j, Pa);
+                chord_pieces<R, DIM>(J, Ip, Pa, Ie, Pe, wk, close);
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                Ip[d] = Ie[d];
+                fp[d] = fe[d];
+            }
+        }
+    }
+    stitch(out, rc, wk, c, P, ctot, col_start, lane, (n - 1) / K);
 }
 
 // Walk one row with the whole wave, in three phases that hold only their own data:
@@ -708,20 +829,10 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowW<R> &w, int 
     rc.O = 0.f;
     rc.open_col = -1;
     rc.any = false;
-    if (w.lo0 < w.hi0) {
-        RayW<R> r;
-        ray_prepare<R, DIM>(J, w.A0, w.D0, w.lo0, w.hi0, r);
-        uni_ray(r);
-        walk_cells<R, DIM, KR, TW>(J, r, out, rc, lane);
-    }
+    walk_cells<R, DIM, TW>(J, w.ray[0], out, rc, lane);
     if (kind == 2) {
-        walk_chords<R, DIM, KC, TW>(J, w, out, rc, lane);
-        if (w.lo1 < w.hi1) {
-            RayW<R> r;
-            ray_prepare<R, DIM>(J, w.A1, w.D1, w.lo1, w.hi1, r);
-            uni_ray(r);
-            walk_cells<R, DIM, KR, TW>(J, r, out, rc, lane);
-        }
+        walk_chords<R, DIM, TW>(J, w, out, rc, lane);
+        walk_cells<R, DIM, TW>(J, w.ray[1], out, rc, lane);
     }
     if (rc.any) {
         if (lane == 0) out.put((int32_t)rc.C, rc.open_col, rc.O);
@@ -751,14 +862,10 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowW<R> &w
     w.N = 0;
     if (!p.curved) {
         R lo = ninf, hi = pinf;
-        w.kind = clip_box<R, DIM>(J, p.Q, p.u, lo, hi) ? 1 : 0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            w.A0[d] = p.Q[d];
-            w.D0[d] = p.u[d];
-        }
-        w.lo0 = lo;
-        w.hi0 = hi;
+        const bool hit = clip_box<R, DIM>(J, p.Q, p.u, lo, hi);
+        w.kind = hit ? 1 : 0;
+        if (!hit) { lo = R(1); hi = R(0); }
+        ray_prepare<R, DIM>(J, p.Q, p.u, lo, hi, w.ray[0]);
     } else {
         // the spline lies in the convex hull of its Bezier control points
         R b1[3], b2[3];
@@ -772,19 +879,13 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowW<R> &w
         w.kind = in ? 2 : 3;
         R lo = ninf, hi = R(0);
         if (!clip_box<R, DIM>(J, p.P0, p.d0, lo, hi)) { lo = R(1); hi = R(0); }
-        w.lo0 = lo;
-        w.hi0 = hi;
+        ray_prepare<R, DIM>(J, p.P0, p.d0, lo, hi, w.ray[0]);
         lo = R(0);
         hi = pinf;
         if (!clip_box<R, DIM>(J, p.P1, p.d1, lo, hi)) { lo = R(1); hi = R(0); }
-        w.lo1 = lo;
-        w.hi1 = hi;
+        ray_prepare<R, DIM>(J, p.P1, p.d1, lo, hi, w.ray[1]);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            w.A0[d] = p.P0[d];
-            w.D0[d] = p.d0[d];
-            w.A1[d] = p.P1[d];
-            w.D1[d] = p.d1[d];
             w.c1[d] = p.c1[d];
             w.c2[d] = p.c2[d];
             w.c3[d] = p.c3[d];
@@ -811,13 +912,11 @@ __device__ __forceinline__ int64_t count_row(const JobDev &J, const RowW<R> &w, 
         trace_row<R, DIM, true>(J, g, s);
         return s.n;
     }
-    RayW<R> r;
     int64_t c = 0;
     bool any = false;
-    if (w.lo0 < w.hi0) {
-        ray_prepare<R, DIM>(J, w.A0, w.D0, w.lo0, w.hi0, r);
+    if (w.ray[0].ncell > 0) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) c += abs(r.ie[d] - r.is[d]);
+        for (int d = 0; d < DIM; ++d) c += abs(w.ray[0].ie[d] - w.ray[0].is[d]);
         any = true;
     }
     if (w.kind == 2) {
@@ -837,10 +936,9 @@ __device__ __forceinline__ int64_t count_row(const JobDev &J, const RowW<R> &w, 
             }
         }
         any = true;
-        if (w.lo1 < w.hi1) {
-            ray_prepare<R, DIM>(J, w.A1, w.D1, w.lo1, w.hi1, r);
+        if (w.ray[1].ncell > 0) {
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) c += abs(r.ie[d] - r.is[d]);
+            for (int d = 0; d < DIM; ++d) c += abs(w.ray[1].ie[d] - w.ray[1].is[d]);
         }
     }
     return any ? c + 1 : 0;

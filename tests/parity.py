@@ -7,7 +7,8 @@ Bar, per row of the sample:
   * every other row: identical entry count and column sequence (bit-exact);
   * FP32 lengths: |gpu - oracle| <= 1e-5 * max(oracle, h_min);
   * FP16 lengths: within one binary16 ulp of the oracle length rounded to binary32
-    then binary16 (round to nearest even);
+    then binary16 (round to nearest even), or within the FP32 bar plus half a binary16
+    ulp (the storage rounding) -- the second form matters only for tiny pieces;
   * b (every non-excluded row): |gpu - oracle| <= 1e-5 * |oracle| + 1e-6 mm.
 """
 from __future__ import annotations
@@ -67,11 +68,19 @@ def compare(g: dict, o: dict, h_min: float, val_dtype: str, check_b: bool = True
         ol = o["vals"][oa:ob]
         gl = g["vals"][ga:gb]
         if val_dtype == "f16":
+            # within one binary16 ulp of the rounded oracle length, or within the FP32
+            # tolerance plus the binary16 storage rounding (matters for tiny pieces)
             ref = ol.astype(np.float32).astype(np.float16).view(np.uint16).astype(np.int32)
-            got = gl.astype(np.float16).view(np.uint16).astype(np.int32)
+            got16 = gl.astype(np.float16)
+            got = got16.view(np.uint16).astype(np.int32)
             d = np.abs(ref - got)
-            if len(d) and d.max() > 1:
-                bad.append((i, int(o["rows"][i]), "f16 ulp", int(d.max())))
+            half_ulp = np.abs(np.spacing(got16).astype(np.float64)) / 2
+            err = np.abs(got16.astype(np.float64) - ol)
+            okv = (d <= 1) | (err <= LEN_REL * np.maximum(ol, h_min) + half_ulp)
+            if len(d):
+                stats["max_f16_ulp"] = max(stats.get("max_f16_ulp", 0), int(d.max()))
+            if not np.all(okv):
+                bad.append((i, int(o["rows"][i]), "f16", int(d.max()), float(err.max())))
         else:
             err = np.abs(gl.astype(np.float64) - ol)
             lim = LEN_REL * np.maximum(ol, h_min)
