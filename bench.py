@@ -131,6 +131,30 @@ class Pipeline:
         return self.bytes_emit() + 4 * nvox + self.total_rows * (4 * 3 + 8)
 
 
+def stored_traffic(kernel, workload_name):
+    """HBM bytes per launch of `kernel` on this workload from the committed profile
+    summaries (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when
+    no summary exists or the kernels have changed since it was taken."""
+    from paper_2108_12369_amd import build as B
+    digest = B.source_digest()
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for fn in sorted(os.listdir(pdir)):
+        if not fn.endswith(".md"):
+            continue
+        kv = {}
+        with open(os.path.join(pdir, fn)) as fh:
+            for line in fh:
+                if line.startswith("- ") and ":" in line:
+                    k, v = line[2:].split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel") == kernel and kv.get("workload") == workload_name \
+                and kv.get("source_digest") == digest and "traffic_bytes_per_launch" in kv:
+            return float(kv["traffic_bytes_per_launch"])
+    return None
+
+
 def workload(name, W):
     if name == "c3":
         return W.c3_jobs(), None
@@ -228,8 +252,9 @@ def main():
                    "val_dtype": pl.val_dtype[0]},
         "nnz_per_s": pl.total_nnz / (ms_step * 1e-3),
         "step_algorithmic_GBps": pl.bytes_step() / (ms_step * 1e-3) / 1e9,
-        "roofline": {"bound": "hbm", "kernel": "k_emit", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "hbm", "kernel": "k_emit_wave", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (stored_traffic("k_emit_wave", cfgs[0]["name"]) if len(cfgs) == 1 else None),
                      "emit_ms_per_launch": emit_launch_ms, "algorithmic_bytes_per_launch": emit_bytes_launch},
     }
     del pl

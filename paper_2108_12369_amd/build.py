@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpct.so")
 SOURCES = [os.path.join(CSRC, "pct.hip")]
-HEADERS = [os.path.join(CSRC, "pct_device.h"), os.path.join(ROOT, "include", "pct.h")]
+HEADERS = [os.path.join(CSRC, "pct_device.h"), os.path.join(CSRC, "pct_wave.h"),
+           os.path.join(ROOT, "include", "pct.h")]
 
 ARCH = os.environ.get("PCT_OFFLOAD_ARCH", "gfx950")
 
@@ -30,6 +31,20 @@ def hipcc() -> str:
     if not os.path.exists(exe):
         raise RuntimeError("hipcc not found: the HIP library cannot be built")
     return exe
+
+
+def source_digest() -> str:
+    """Short SHA-256 over the device sources, the public header and the compiler flags:
+    identifies the kernels a stored profile was taken from."""
+    import hashlib
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    files += [os.path.join(ROOT, "include", "pct.h")]
+    h = hashlib.sha256(" ".join(FLAGS).encode())
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def build(verbose: bool = False) -> str:
