@@ -38,7 +38,7 @@ struct Layout {
 };
 
 // per-row path descriptions (the larger of the two precisions)
-constexpr size_t ROWW_BYTES = sizeof(RowW<double>) > sizeof(RowW<float>) ? sizeof(RowW<double>) : sizeof(RowW<float>);
+constexpr size_t ROWW_BYTES = sizeof(RowV<double>) > sizeof(RowV<float>) ? sizeof(RowV<double>) : sizeof(RowV<float>);
 
 static Layout layout_of(int32_t n_jobs, const int64_t *row_counts) {
     Layout L{};
@@ -110,7 +110,7 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
 template <typename R, bool COUNT>
 __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs, int n_jobs,
                                                 int32_t *__restrict__ counts, int64_t *__restrict__ tile_sums,
-                                                RowW<R> *__restrict__ rowbuf) {
+                                                RowV<R> *__restrict__ rowbuf) {
     __shared__ int64_t red[TILE / 64];
     const int64_t tile = blockIdx.x;
     const int jid = job_of_tile(jobs, n_jobs, tile);
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs,
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     int64_t cnt = 0;
     if (r < J.row_count) {
-        RowW<R> &w = rowbuf[J.count_off + r];
+        RowV<R> &w = rowbuf[J.count_off + r];
         const int64_t g = J.row_begin + r;
         if (J.dim == 3) setup_row<R, 3>(J, g, w);
         else setup_row<R, 2>(J, g, w);
@@ -193,35 +193,36 @@ __global__ void __launch_bounds__(TILE) k_row_ptr(const JobDev *__restrict__ job
 }
 
 // Wave-cooperative emit: each wavefront of the block takes 64 rows of the tile.
-constexpr int KR2 = 2, KC2 = 4;   // ray cells / spline chords per lane per pass, 2D
-constexpr int KR3 = 2, KC3 = 2;   // ... 3D
 
-template <typename R, bool STORE>
+// One instance per grid dimension (the register needs differ); blocks of jobs of the
+// other dimension return at once.
+template <typename R, bool STORE, int DIM>
 __global__ void __launch_bounds__(TILE) k_emit_wave(const JobDev *__restrict__ jobs, int n_jobs,
-                                                    const RowW<R> *__restrict__ rowbuf,
+                                                    const RowV<R> *__restrict__ rowbuf,
                                                     int32_t *__restrict__ status) {
+    __shared__ uint2 stage[TILE / WAVE][STAGE_CAP];
     const int64_t tile = blockIdx.x;
     const int jid = job_of_tile(jobs, n_jobs, tile);
     const JobDev &J = jobs[jid];
+    if (J.dim != DIM) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int lane = threadIdx.x % WAVE;
     const int64_t r0 = (tile - J.tile_base) * TILE + wave * WAVE;
-    const RowW<R> *rows = rowbuf + J.count_off;
-    if (J.dim == 3) emit_rows_wave<R, 3, KR3, KC3, STORE>(J, rows, r0, lane, status);
-    else emit_rows_wave<R, 2, KR2, KC2, STORE>(J, rows, r0, lane, status);
+    const RowV<R> *rows = rowbuf + J.count_off;
+    emit_rows_wave<R, DIM, STORE>(J, rows, r0, lane, stage[wave], status);
 }
 
 // Rows whose spline may leave the grid box: one lane per row.
 template <typename R, bool STORE>
 __global__ void __launch_bounds__(TILE) k_emit_lane(const JobDev *__restrict__ jobs, int n_jobs,
-                                                    const RowW<R> *__restrict__ rowbuf,
+                                                    const RowV<R> *__restrict__ rowbuf,
                                                     int32_t *__restrict__ status) {
     const int64_t tile = blockIdx.x;
     const int jid = job_of_tile(jobs, n_jobs, tile);
     const JobDev &J = jobs[jid];
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     if (r >= J.row_count) return;
-    const RowW<R> &w = rowbuf[J.count_off + r];
+    const RowV<R> &w = rowbuf[J.count_off + r];
     if (w.kind != 3) return;
     if (J.dim == 3) emit_row_lane<R, 3, STORE>(J, w, r, status);
     else emit_row_lane<R, 2, STORE>(J, w, r, status);
@@ -521,10 +522,10 @@ pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
     if (T > 0) {
         if (jobs[0].precision == PCT_MIXED)
             hipLaunchKernelGGL((k_count<double, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums,
-                               (RowW<double> *)(w + P.L.rows_off));
+                               (RowV<double> *)(w + P.L.rows_off));
         else
             hipLaunchKernelGGL((k_count<float, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums,
-                               (RowW<float> *)(w + P.L.rows_off));
+                               (RowV<float> *)(w + P.L.rows_off));
     }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_THREADS), 0, s, J, n_jobs, T, sums, offs, nnz_total_dev);
     if (T > 0) hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, offs);
@@ -547,26 +548,35 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
     const int64_t T = P.L.total_tiles;
     if (T == 0) return PCT_OK;
     const bool mixed = jobs[0].precision == PCT_MIXED;
+    bool has2 = false, has3 = false;
+    for (int j = 0; j < n_jobs; ++j) {
+        if (jobs[j].beam->row_count == 0) continue;
+        (jobs[j].phantom->dim == 3 ? has3 : has2) = true;
+    }
     void *rows = w + P.L.rows_off;
     const dim3 grid((unsigned)T), block(TILE);
     if (mixed) {
-        RowW<double> *rb = (RowW<double> *)rows;
+        RowV<double> *rb = (RowV<double> *)rows;
         if (!store) hipLaunchKernelGGL((k_count<double, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, rb);
         if (store) {
-            hipLaunchKernelGGL((k_emit_wave<double, true>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has2) hipLaunchKernelGGL((k_emit_wave<double, true, 2>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has3) hipLaunchKernelGGL((k_emit_wave<double, true, 3>), grid, block, 0, s, J, n_jobs, rb, status);
             hipLaunchKernelGGL((k_emit_lane<double, true>), grid, block, 0, s, J, n_jobs, rb, status);
         } else {
-            hipLaunchKernelGGL((k_emit_wave<double, false>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has2) hipLaunchKernelGGL((k_emit_wave<double, false, 2>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has3) hipLaunchKernelGGL((k_emit_wave<double, false, 3>), grid, block, 0, s, J, n_jobs, rb, status);
             hipLaunchKernelGGL((k_emit_lane<double, false>), grid, block, 0, s, J, n_jobs, rb, status);
         }
     } else {
-        RowW<float> *rb = (RowW<float> *)rows;
+        RowV<float> *rb = (RowV<float> *)rows;
         if (!store) hipLaunchKernelGGL((k_count<float, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, rb);
         if (store) {
-            hipLaunchKernelGGL((k_emit_wave<float, true>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has2) hipLaunchKernelGGL((k_emit_wave<float, true, 2>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has3) hipLaunchKernelGGL((k_emit_wave<float, true, 3>), grid, block, 0, s, J, n_jobs, rb, status);
             hipLaunchKernelGGL((k_emit_lane<float, true>), grid, block, 0, s, J, n_jobs, rb, status);
         } else {
-            hipLaunchKernelGGL((k_emit_wave<float, false>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has2) hipLaunchKernelGGL((k_emit_wave<float, false, 2>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has3) hipLaunchKernelGGL((k_emit_wave<float, false, 3>), grid, block, 0, s, J, n_jobs, rb, status);
             hipLaunchKernelGGL((k_emit_lane<float, false>), grid, block, 0, s, J, n_jobs, rb, status);
         }
     }
