@@ -32,6 +32,9 @@ def parse():
     ap.add_argument("--workload", default="c1", help="c0 | c1 | c2 | c3 | c4 | paper")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched (64 uneven jobs, one graph) vs plain single-phantom comparison")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample size (0: auto)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for HBM byte counters)")
@@ -41,18 +44,21 @@ def parse():
 class Pipeline:
     """Pre-allocated buffers for a list of jobs (optionally split in row chunks)."""
 
-    def __init__(self, P, cfgs, precision="mixed", chunk_rows=None, val_dtype=None):
+    def __init__(self, P, cfgs, precision="mixed", chunk_rows=None, val_dtype=None, per_job=False):
         import torch
         self.P, self.torch = P, torch
         self.cfgs = cfgs
         self.precision = precision
         self.val_dtype = [val_dtype or c.get("val_dtype", "f32") for c in cfgs]
         self.xs = [P.phantom_build(c["phantom"]) for c in cfgs]
-        # chunks: list of lists of (job index, row_begin, row_count)
+        self.graph = None
+        # chunks: list of lists of (job index, row_begin, row_count); one call set per chunk
         if chunk_rows:
             assert len(cfgs) == 1
             n = cfgs[0]["beam"]["n_protons"]
             self.chunks = [[(0, rb, min(chunk_rows, n - rb))] for rb in range(0, n, chunk_rows)]
+        elif per_job:
+            self.chunks = [[(j, 0, c["beam"]["n_protons"])] for j, c in enumerate(cfgs)]
         else:
             self.chunks = [[(j, 0, c["beam"]["n_protons"]) for j, c in enumerate(cfgs)]]
         max_rows = {}
@@ -99,8 +105,35 @@ class Pipeline:
         js.array()
         return js
 
+    def autotune(self):
+        """Pick the launch configuration on this workload (the first chunk)."""
+        return self.P.autotune(self.emit_sets[0], self.ws, self.nnz)
+
+    def capture(self):
+        """Record the whole step (phantoms, count, emit) in one HIP graph."""
+        assert len(self.chunks) == 1
+        self.graph = self.P.Graph(self.emit_sets[0], self.ws, self.nnz, build_x=True)
+
+    def emit_only(self, reps=3):
+        """Average emit duration (ms) per chunk, HIP events on the launch stream."""
+        torch = self.torch
+        ts = []
+        for _ in range(reps):
+            for k in range(len(self.chunks)):
+                self.P.count_rows(self.count_sets[k], self.ws, self.nnz)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                self.P.emit_csr(self.emit_sets[k], self.ws)
+                e1.record()
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+        return float(np.mean(ts))
+
     def step(self, emit_events=None):
         P = self.P
+        if self.graph is not None:
+            self.graph.launch()
+            return
         for j, c in enumerate(self.cfgs):
             P.phantom_build(c["phantom"], self.xs[j])
         for k in range(len(self.chunks)):
@@ -199,6 +232,39 @@ def cpu_baseline(cfgs, n_rows_target):
     return rows_done, nnz_done, secs
 
 
+def batched_vs_single(P, W, steps, warmup, tune):
+    """The 64 uneven jobs of the batched workload: mixed precision in one launch set
+    captured as a HIP graph (autotuned), against plain FP32 with one call set per job."""
+    import torch
+    jobs = W.c3_jobs()
+    out = {}
+    pb = Pipeline(P, jobs, "mixed")
+    cfg = pb.autotune() if tune else P.get_launch_config()
+    pb.capture()
+    dt, _ = time_pipeline(pb, steps, warmup)
+    ms = 1e3 * dt / steps
+    emit_ms = pb.emit_only()
+    gbs = pb.bytes_emit() / (emit_ms * 1e-3) / 1e9
+    out["batched"] = {"workload": f"c3-{len(jobs)}-uneven-jobs-graph", "rows": pb.total_rows, "nnz": pb.total_nnz,
+                      "protons_per_s": pb.total_rows / (ms * 1e-3), "nnz_per_s": pb.total_nnz / (ms * 1e-3),
+                      "ms_per_step": ms, "emit_ms": emit_ms, "emit_GBps": gbs, "emit_frac": gbs / HBM_PEAK_GBS,
+                      "launch": cfg, "precision": "mixed, FP16 stored lengths"}
+    del pb
+    torch.cuda.empty_cache()
+    P.set_launch_config()
+    ps = Pipeline(P, jobs, "plain_f32", val_dtype="f32", per_job=True)
+    dt, _ = time_pipeline(ps, steps, warmup)
+    ms = 1e3 * dt / steps
+    out["plain_single"] = {"workload": f"c3-{len(jobs)}-uneven-jobs-one-by-one", "rows": ps.total_rows,
+                           "nnz": ps.total_nnz, "protons_per_s": ps.total_rows / (ms * 1e-3),
+                           "nnz_per_s": ps.total_nnz / (ms * 1e-3), "ms_per_step": ms,
+                           "precision": "plain FP32, FP32 stored lengths"}
+    out["batched_mixed_over_plain_single"] = out["batched"]["protons_per_s"] / out["plain_single"]["protons_per_s"]
+    del ps
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -226,6 +292,7 @@ def main():
 
     cfgs, chunk = workload(args.workload, W)
     pl = Pipeline(P, cfgs, "mixed", chunk)
+    tuned = None if args.no_tune else pl.autotune()
     dt, emit_ms = time_pipeline(pl, args.steps, args.warmup)
     ms_step = 1e3 * dt / args.steps
     rows = pl.total_rows
@@ -249,7 +316,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfgs[0]["name"] if len(cfgs) == 1 else f"c3-batched-{len(cfgs)}-jobs",
                    "jobs": len(cfgs), "rows": rows, "nnz": pl.total_nnz, "chunks": len(pl.chunks),
-                   "val_dtype": pl.val_dtype[0]},
+                   "val_dtype": pl.val_dtype[0], "launch": tuned or P.get_launch_config()},
         "nnz_per_s": pl.total_nnz / (ms_step * 1e-3),
         "step_algorithmic_GBps": pl.bytes_step() / (ms_step * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "kernel": "k_emit_wave", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -272,6 +339,9 @@ def main():
         res["mixed_over_plain"] = res["value"] / res["plain_f32"]["protons_per_s"]
         del plf
         torch.cuda.empty_cache()
+
+    if not args.no_batched:
+        res.update(batched_vs_single(P, W, args.steps, args.warmup, not args.no_tune))
 
     if not args.no_cpu:
         target = args.cpu_rows

@@ -168,6 +168,47 @@ pct_status pct_wepl(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_t ws
  * PCT_OK, PCT_ECAPACITY or PCT_EINTERNAL (first error since the last count pass). */
 pct_status pct_device_status(const void *ws_dev, void *stream);
 
+/* ------------------------------------------------------------- batched launches
+ * Many jobs (phantoms, grids, beams of uneven size) share one launch of every kernel
+ * of a pass.  How the emit pass spreads them over the GPU is set by a process-wide
+ * launch configuration (read when a call is enqueued; set it between calls, not
+ * during them).  It does not change any output: every row is computed the same way
+ * whatever the order or grouping of the rows. */
+#define PCT_ORDER_GIVEN 0   /* emit tiles in the order of the job array                 */
+#define PCT_ORDER_LPT   1   /* jobs with the costliest rows first (longest processing   */
+                            /* time first), so that cheap tiles fill the tail           */
+
+typedef struct {
+    int32_t rows_per_wave;  /* 16, 32 or 64: consecutive rows walked by one wavefront    */
+    int32_t order;          /* PCT_ORDER_GIVEN | PCT_ORDER_LPT                           */
+} pct_launch_config;
+
+/* Set (NULL: reset to the default {64, PCT_ORDER_LPT}) or read the configuration. */
+pct_status pct_set_launch_config(const pct_launch_config *cfg);
+pct_status pct_get_launch_config(pct_launch_config *cfg);
+
+/* Autotuner: runs pct_count_rows once and then pct_emit_csr with every candidate
+ * configuration (rows_per_wave 16/32/64 x both orders), timing each emit with HIP
+ * events on `stream` (this call synchronises it), keeps the fastest as the process-wide
+ * configuration and returns it in *best.  The jobs must be ready for pct_emit_csr
+ * (outputs sized from an earlier count); their outputs hold a complete, valid result
+ * afterwards. */
+pct_status pct_autotune(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_t ws_bytes,
+                        int64_t *nnz_total_dev, void *stream, pct_launch_config *best);
+
+/* A whole batch recorded once into a HIP graph and replayed with one call: optionally
+ * the voxelisation of every job's phantom into its x_dev (build_x != 0; jobs that share
+ * an x_dev build it once), then pct_count_rows and pct_emit_csr for all jobs.  The
+ * descriptors and the launch configuration are captured at creation: a replay writes
+ * the same outputs as the eager calls would.  The graph owns no device memory; the
+ * caller's buffers and workspace must outlive it.  Creation runs the host validation of
+ * the calls and returns its status; nothing is enqueued on any caller stream. */
+typedef struct pct_graph_s *pct_graph;
+pct_status pct_graph_create(int32_t n_jobs, const pct_job *jobs, int32_t build_x, void *ws_dev,
+                            size_t ws_bytes, int64_t *nnz_total_dev, pct_graph *graph);
+pct_status pct_graph_launch(pct_graph graph, void *stream);
+pct_status pct_graph_destroy(pct_graph graph);
+
 #ifdef __cplusplus
 }
 #endif

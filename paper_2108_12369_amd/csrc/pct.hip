@@ -16,6 +16,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 namespace pct {
@@ -33,7 +34,7 @@ struct WsHeader {
 static inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t jobs_off, sums_off, offs_off, counts_off, rows_off, total;
+    size_t jobs_off, order_off, sums_off, offs_off, counts_off, rows_off, total;
     int64_t total_tiles, total_rows;
 };
 
@@ -50,7 +51,8 @@ static Layout layout_of(int32_t n_jobs, const int64_t *row_counts) {
     L.total_tiles = tiles;
     L.total_rows = rows;
     L.jobs_off = align256(sizeof(WsHeader));
-    L.sums_off = align256(L.jobs_off + (size_t)n_jobs * sizeof(JobDev));
+    L.order_off = align256(L.jobs_off + (size_t)n_jobs * sizeof(JobDev));
+    L.sums_off = align256(L.order_off + (size_t)n_jobs * sizeof(int32_t));
     L.offs_off = align256(L.sums_off + (size_t)(tiles + 1) * sizeof(int64_t));
     L.counts_off = align256(L.offs_off + (size_t)(tiles + 1) * sizeof(int64_t));
     L.rows_off = align256(L.counts_off + (size_t)rows * sizeof(int32_t));
@@ -76,6 +78,17 @@ __global__ void k_put_jobs(JobDev *dst, JobPack pack) {
     for (int w = threadIdx.x; w < words; w += blockDim.x) out[w] = src[w];
 }
 
+constexpr int ORDER_PER_PACK = 900;
+struct OrderPack {
+    int32_t count;
+    int32_t first;
+    int32_t idx[ORDER_PER_PACK];
+};
+
+__global__ void k_put_order(int32_t *dst, OrderPack pack) {
+    for (int i = threadIdx.x; i < pack.count; i += blockDim.x) dst[pack.first + i] = pack.idx[i];
+}
+
 __global__ void k_clear_status(WsHeader *h) {
     if (threadIdx.x == 0) h->status = PCT_OK;
 }
@@ -91,6 +104,18 @@ __device__ __forceinline__ int job_of_tile(const JobDev *jobs, int n_jobs, int64
         else hi = mid - 1;
     }
     return lo;
+}
+
+// Emit tile -> job: the jobs are laid out in launch order (eorder); binary search on
+// their etile_base.
+__device__ __forceinline__ int job_of_etile(const JobDev *jobs, const int32_t *eorder, int n_jobs, int64_t tile) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[eorder[mid]].etile_base <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return eorder[lo];
 }
 
 __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
@@ -195,21 +220,21 @@ __global__ void __launch_bounds__(TILE) k_row_ptr(const JobDev *__restrict__ job
 // Wave-cooperative emit: each wavefront of the block takes 64 rows of the tile.
 
 // One instance per grid dimension (the register needs differ); blocks of jobs of the
-// other dimension return at once.
+// other dimension return at once.  A block is one emit tile: 4 waves of rpw rows.
 template <typename R, bool STORE, int DIM>
-__global__ void __launch_bounds__(TILE) k_emit_wave(const JobDev *__restrict__ jobs, int n_jobs,
-                                                    const RowV<R> *__restrict__ rowbuf,
+__global__ void __launch_bounds__(TILE) k_emit_wave(const JobDev *__restrict__ jobs, const int32_t *__restrict__ eorder,
+                                                    int n_jobs, const RowV<R> *__restrict__ rowbuf,
                                                     int32_t *__restrict__ status) {
-    __shared__ uint2 stage[TILE / WAVE][STAGE_CAP];
+    __shared__ uint2 stage[TILE / WAVE][STAGE_CAP + 1];   // 1024 entries per wave
     const int64_t tile = blockIdx.x;
-    const int jid = job_of_tile(jobs, n_jobs, tile);
+    const int jid = job_of_etile(jobs, eorder, n_jobs, tile);
     const JobDev &J = jobs[jid];
     if (J.dim != DIM) return;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int lane = threadIdx.x % WAVE;
-    const int64_t r0 = (tile - J.tile_base) * TILE + wave * WAVE;
+    const int64_t r0 = ((tile - J.etile_base) * (TILE / WAVE) + wave) * J.rpw;
     const RowV<R> *rows = rowbuf + J.count_off;
-    emit_rows_wave<R, DIM, STORE>(J, rows, r0, lane, stage[wave], status);
+    emit_rows_wave<R, DIM, STORE>(J, rows, r0, J.rpw, lane, stage[wave], status);
 }
 
 // Rows whose spline may leave the grid box: one lane per row.
@@ -411,14 +436,41 @@ static JobDev make_job(const pct_job &jb, int64_t count_off, int64_t tile_base) 
     J.count_off = count_off;
     J.tile_base = tile_base;
     J.n_tiles = (bm.row_count + TILE - 1) / TILE;
+    J.nmax = J.n[0] > J.n[1] ? J.n[0] : J.n[1];
+    J.nmax = J.n[2] > J.nmax ? J.n[2] : J.nmax;
     return J;
+}
+
+// Process-wide launch configuration of the emit pass (read-mostly).
+static pct_launch_config g_cfg = {64, PCT_ORDER_LPT};
+
+static bool config_ok(const pct_launch_config &c) {
+    return (c.rows_per_wave == 16 || c.rows_per_wave == 32 || c.rows_per_wave == 64) &&
+           (c.order == PCT_ORDER_GIVEN || c.order == PCT_ORDER_LPT);
+}
+
+// Relative cost of one row of a job: voxels a path crosses (about the sum of the grid
+// sizes) plus, for spline paths, the samples over an outer-boundary diameter.
+static double row_cost(const pct_job &jb) {
+    const pct_phantom &ph = *jb.phantom;
+    double c = 0.0;
+    for (int d = 0; d < ph.dim; ++d) c += ph.n[d];
+    if (jb.beam->path == PCT_HERMITE) {
+        double smax = 0.0;
+        for (int i = 0; i < 3; ++i) smax = fmax(smax, ph.regions[0].semi[i]);
+        c += 2.0 * smax / jb.beam->step_mm;
+    }
+    return c;
 }
 
 struct Prepared {
     Layout L;
     std::vector<JobDev> jobs;
+    int64_t total_etiles = 0;
 };
 
+// Job table (caller's order; the count pass uses it as is) and the emit launch order,
+// both uploaded through kernel arguments.
 static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, Prepared &P,
                           hipStream_t st) {
     std::vector<int64_t> rc(n_jobs);
@@ -432,7 +484,26 @@ static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
         count_off += rc[j];
         tile_base += P.jobs[j].n_tiles;
     }
-    JobDev *dst = reinterpret_cast<JobDev *>((char *)ws + P.L.jobs_off);
+    const pct_launch_config cfg = g_cfg;
+    std::vector<int32_t> order(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) order[j] = j;
+    if (cfg.order == PCT_ORDER_LPT) {
+        std::vector<double> cost(n_jobs);
+        for (int j = 0; j < n_jobs; ++j) cost[j] = row_cost(jobs[j]);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    }
+    const int64_t rows_per_etile = (int64_t)(TILE / WAVE) * cfg.rows_per_wave;
+    int64_t etile = 0;
+    for (int k = 0; k < n_jobs; ++k) {
+        JobDev &J = P.jobs[order[k]];
+        J.rpw = cfg.rows_per_wave;
+        J.etile_base = etile;
+        J.n_etiles = (J.row_count + rows_per_etile - 1) / rows_per_etile;
+        etile += J.n_etiles;
+    }
+    P.total_etiles = etile;
+    char *w = (char *)ws;
+    JobDev *dst = reinterpret_cast<JobDev *>(w + P.L.jobs_off);
     for (int first = 0; first < n_jobs; first += JOBS_PER_PACK) {
         JobPack pack;
         memset(&pack, 0, sizeof pack);
@@ -440,6 +511,15 @@ static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
         pack.count = (n_jobs - first < JOBS_PER_PACK) ? n_jobs - first : JOBS_PER_PACK;
         for (int k = 0; k < pack.count; ++k) pack.jobs[k] = P.jobs[first + k];
         hipLaunchKernelGGL(k_put_jobs, dim3(1), dim3(256), 0, st, dst, pack);
+    }
+    int32_t *odst = reinterpret_cast<int32_t *>(w + P.L.order_off);
+    for (int first = 0; first < n_jobs; first += ORDER_PER_PACK) {
+        OrderPack pack;
+        memset(&pack, 0, sizeof pack);
+        pack.first = first;
+        pack.count = (n_jobs - first < ORDER_PER_PACK) ? n_jobs - first : ORDER_PER_PACK;
+        for (int k = 0; k < pack.count; ++k) pack.idx[k] = order[first + k];
+        hipLaunchKernelGGL(k_put_order, dim3(1), dim3(256), 0, st, odst, pack);
     }
     return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
 }
@@ -553,30 +633,31 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
         if (jobs[j].beam->row_count == 0) continue;
         (jobs[j].phantom->dim == 3 ? has3 : has2) = true;
     }
+    const int32_t *eorder = (const int32_t *)(w + P.L.order_off);
     void *rows = w + P.L.rows_off;
-    const dim3 grid((unsigned)T), block(TILE);
+    const dim3 grid((unsigned)T), egrid((unsigned)P.total_etiles), block(TILE);
     if (mixed) {
         RowV<double> *rb = (RowV<double> *)rows;
         if (!store) hipLaunchKernelGGL((k_count<double, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, rb);
         if (store) {
-            if (has2) hipLaunchKernelGGL((k_emit_wave<double, true, 2>), grid, block, 0, s, J, n_jobs, rb, status);
-            if (has3) hipLaunchKernelGGL((k_emit_wave<double, true, 3>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has2) hipLaunchKernelGGL((k_emit_wave<double, true, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
+            if (has3) hipLaunchKernelGGL((k_emit_wave<double, true, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
             hipLaunchKernelGGL((k_emit_lane<double, true>), grid, block, 0, s, J, n_jobs, rb, status);
         } else {
-            if (has2) hipLaunchKernelGGL((k_emit_wave<double, false, 2>), grid, block, 0, s, J, n_jobs, rb, status);
-            if (has3) hipLaunchKernelGGL((k_emit_wave<double, false, 3>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has2) hipLaunchKernelGGL((k_emit_wave<double, false, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
+            if (has3) hipLaunchKernelGGL((k_emit_wave<double, false, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
             hipLaunchKernelGGL((k_emit_lane<double, false>), grid, block, 0, s, J, n_jobs, rb, status);
         }
     } else {
         RowV<float> *rb = (RowV<float> *)rows;
         if (!store) hipLaunchKernelGGL((k_count<float, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, rb);
         if (store) {
-            if (has2) hipLaunchKernelGGL((k_emit_wave<float, true, 2>), grid, block, 0, s, J, n_jobs, rb, status);
-            if (has3) hipLaunchKernelGGL((k_emit_wave<float, true, 3>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has2) hipLaunchKernelGGL((k_emit_wave<float, true, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
+            if (has3) hipLaunchKernelGGL((k_emit_wave<float, true, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
             hipLaunchKernelGGL((k_emit_lane<float, true>), grid, block, 0, s, J, n_jobs, rb, status);
         } else {
-            if (has2) hipLaunchKernelGGL((k_emit_wave<float, false, 2>), grid, block, 0, s, J, n_jobs, rb, status);
-            if (has3) hipLaunchKernelGGL((k_emit_wave<float, false, 3>), grid, block, 0, s, J, n_jobs, rb, status);
+            if (has2) hipLaunchKernelGGL((k_emit_wave<float, false, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
+            if (has3) hipLaunchKernelGGL((k_emit_wave<float, false, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
             hipLaunchKernelGGL((k_emit_lane<float, false>), grid, block, 0, s, J, n_jobs, rb, status);
         }
     }
@@ -589,6 +670,136 @@ pct_status pct_emit_csr(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws
 
 pct_status pct_wepl(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, void *stream) {
     return emit_common(n_jobs, jobs, ws, ws_bytes, stream, false);
+}
+
+pct_status pct_set_launch_config(const pct_launch_config *cfg) {
+    if (!cfg) {
+        g_cfg = pct_launch_config{64, PCT_ORDER_LPT};
+        return PCT_OK;
+    }
+    if (!config_ok(*cfg)) return PCT_EINVAL;
+    g_cfg = *cfg;
+    return PCT_OK;
+}
+
+pct_status pct_get_launch_config(pct_launch_config *cfg) {
+    if (!cfg) return PCT_EINVAL;
+    *cfg = g_cfg;
+    return PCT_OK;
+}
+
+pct_status pct_autotune(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, int64_t *nnz_total_dev,
+                        void *stream, pct_launch_config *best) {
+    if (!best) return PCT_EINVAL;
+    pct_status st = check_jobs(n_jobs, jobs, true, false);
+    if (st != PCT_OK) return st;
+    const pct_launch_config saved = g_cfg;
+    hipStream_t s = (hipStream_t)stream;
+    st = pct_count_rows(n_jobs, jobs, ws, ws_bytes, nnz_total_dev, stream);
+    if (st != PCT_OK) return st;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return PCT_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return PCT_EHIP;
+    }
+    const int rpws[3] = {16, 32, 64};
+    const int orders[2] = {PCT_ORDER_GIVEN, PCT_ORDER_LPT};
+    float best_ms = -1.f;
+    pct_launch_config pick = saved;
+    for (int o = 0; o < 2 && st == PCT_OK; ++o) {
+        for (int r = 0; r < 3 && st == PCT_OK; ++r) {
+            g_cfg = pct_launch_config{rpws[r], orders[o]};
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && st == PCT_OK; ++rep) {
+                if (hipEventRecord(e0, s) != hipSuccess) st = PCT_EHIP;
+                if (st == PCT_OK) st = pct_emit_csr(n_jobs, jobs, ws, ws_bytes, stream);
+                if (st == PCT_OK && hipEventRecord(e1, s) != hipSuccess) st = PCT_EHIP;
+                if (st == PCT_OK && hipEventSynchronize(e1) != hipSuccess) st = PCT_EHIP;
+                if (st == PCT_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = PCT_EHIP;
+            }
+            if (st == PCT_OK && (best_ms < 0.f || ms < best_ms)) {
+                best_ms = ms;
+                pick = g_cfg;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_cfg = (st == PCT_OK) ? pick : saved;
+    if (st == PCT_OK) st = pct_emit_csr(n_jobs, jobs, ws, ws_bytes, stream);   // final outputs
+    *best = g_cfg;
+    return st;
+}
+
+}  // extern "C"
+
+struct pct_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+pct_status pct_graph_create(int32_t n_jobs, const pct_job *jobs, int32_t build_x, void *ws, size_t ws_bytes,
+                            int64_t *nnz_total_dev, pct_graph *graph) {
+    if (!graph) return PCT_EINVAL;
+    *graph = nullptr;
+    pct_status st = check_jobs(n_jobs, jobs, true, false);
+    if (st != PCT_OK) return st;
+    if (n_jobs > 0 && !nnz_total_dev) return PCT_EINVAL;
+    if (build_x) {
+        for (int j = 0; j < n_jobs; ++j)
+            if (!jobs[j].x_dev) return PCT_EINVAL;
+    }
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PCT_EHIP;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return PCT_EHIP;
+    }
+    if (build_x) {
+        std::vector<const float *> done;
+        for (int j = 0; j < n_jobs && st == PCT_OK; ++j) {
+            const float *x = jobs[j].x_dev;
+            if (std::find(done.begin(), done.end(), x) != done.end()) continue;
+            done.push_back(x);
+            st = pct_phantom_build(jobs[j].phantom, const_cast<float *>(x), s);
+        }
+    }
+    if (st == PCT_OK) st = pct_count_rows(n_jobs, jobs, ws, ws_bytes, nnz_total_dev, s);
+    if (st == PCT_OK) st = pct_emit_csr(n_jobs, jobs, ws, ws_bytes, s);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    (void)hipStreamDestroy(s);
+    if (st == PCT_OK && ec != hipSuccess) st = PCT_EHIP;
+    if (st != PCT_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    hipGraphExec_t e = nullptr;
+    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return PCT_EHIP;
+    }
+    pct_graph h = new pct_graph_s;
+    h->graph = g;
+    h->exec = e;
+    *graph = h;
+    return PCT_OK;
+}
+
+pct_status pct_graph_launch(pct_graph graph, void *stream) {
+    if (!graph || !graph->exec) return PCT_EINVAL;
+    return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? PCT_OK : PCT_EHIP;
+}
+
+pct_status pct_graph_destroy(pct_graph graph) {
+    if (!graph) return PCT_OK;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+    return PCT_OK;
 }
 
 pct_status pct_device_status(const void *ws, void *stream) {

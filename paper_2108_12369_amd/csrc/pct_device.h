@@ -48,8 +48,12 @@ struct JobDev {
     float *b;
     int64_t cap;
     int64_t count_off;   // first element of this job in the workspace count array
-    int64_t tile_base;   // first tile of this job
+    int64_t tile_base;   // first tile of this job (count pass: TILE rows per tile)
     int64_t n_tiles;
+    int64_t etile_base;  // first emit tile of this job (emit tiles are laid out in the
+    int64_t n_etiles;    // launch order of the jobs, 4 * rpw rows each)
+    int32_t rpw;         // rows per wavefront in the emit pass
+    int32_t nmax;        // largest n[d]
 };
 
 // ------------------------------------------------------------------ math helpers

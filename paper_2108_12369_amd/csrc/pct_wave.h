@@ -228,8 +228,10 @@ struct LaneP {
     int32_t M;
 };
 
+// The index range is kept inside the grid whatever the description holds, so that no
+// column can leave x.
 template <typename R, int DIM>
-__device__ __forceinline__ void lane_ray(const RayP<R> &r, LaneP<R> &p) {
+__device__ __forceinline__ void lane_ray(const JobDev &J, const RayP<R> &r, LaneP<R> &p) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         p.c0[d] = r.c0[d];
@@ -238,8 +240,11 @@ __device__ __forceinline__ void lane_ray(const RayP<R> &r, LaneP<R> &p) {
         p.c3[d] = R(0);
         p.fS[d] = r.fS[d];
         p.fE[d] = r.fE[d];
-        p.lo[d] = R(r.lo[d]);
-        p.hi[d] = R(r.hi[d]);
+        const int top = J.n[d] - 1;
+        const int lo = r.lo[d] < 0 ? 0 : (r.lo[d] > top ? top : r.lo[d]);
+        const int hi = r.hi[d] < lo ? lo : (r.hi[d] > top ? top : r.hi[d]);
+        p.lo[d] = R(lo);
+        p.hi[d] = R(hi);
     }
     p.M = r.M;
 }
@@ -367,14 +372,39 @@ __device__ __forceinline__ void wave_seg_scan(float &v, int &f) {
     seg_step<0x143, 0xc, false>(v, f);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;
+// DPP move of a 64-bit value (two 32-bit moves with the same control).
+template <int CTRL, int ROWMASK, bool BOUND>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWMASK, 0xf, BOUND);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWMASK, 0xf, BOUND);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Entries a wavefront keeps in LDS per row (8 B each: column, FP32 length).
-constexpr int STAGE_CAP = 1024;
+// Sum over the wavefront (the same DPP steps as the integer scan; the total ends in
+// lane 63), returned to every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_f64<0x111, 0xf, true>(v);
+    v += dpp_f64<0x112, 0xf, true>(v);
+    v += dpp_f64<0x114, 0xf, true>(v);
+    v += dpp_f64<0x118, 0xf, true>(v);
+    v += dpp_f64<0x142, 0xa, false>(v);
+    v += dpp_f64<0x143, 0xc, false>(v);
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, WAVE - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), WAVE - 1);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Value of the previous lane (lane 0: 0), DPP wave_shr:1.
+__device__ __forceinline__ float lane_prev(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+
+// Entries a wavefront keeps in LDS per row (8 B each: column, FP32 length).  The slice
+// holds STAGE_CAP + 1 = 1024 entries (a power of two, so an index is kept inside it by
+// a mask); a block of four waves uses 32 KiB.
+constexpr int STAGE_CAP = 1023;
 
 // Output of one row: entries at row-relative indices [0, len) of the row's slices of
 // cols / vals.  A row of at most STAGE_CAP entries is staged in the wave's LDS slice and
@@ -388,14 +418,28 @@ struct RowOut {
     float *vf;
     const float *x;
     uint2 *stage;   // the wave's LDS slice
+    uint32_t nvox;  // size of x: staged columns are checked against it before a gather
     int32_t len;
     float wepl;
     TW wacc;
     bool store, half, want_b, staged;
+    bool bad;       // a lane closed another number of entries than it counted
 
+    // Entry `rel` if `ok`.  A staged row writes slot `rel` on every lane without a
+    // branch: a lane without an entry writes the slot of its next entry, which a later
+    // store of the wave (this lane's next entry, the head of the next lane with a
+    // crossing, or the row's last entry) overwrites in program order.
+    __device__ __forceinline__ void put_if(bool ok, int32_t rel, int32_t col, float l) {
+        if (staged) {
+            // the mask keeps even an inconsistent row inside the wave's own slice
+            stage[(uint32_t)rel & (uint32_t)STAGE_CAP] = make_uint2((uint32_t)col, __float_as_uint(l));
+            return;
+        }
+        if (ok) put(rel, col, l);
+    }
     __device__ __forceinline__ void put(int32_t rel, int32_t col, float l) {
         if (staged) {
-            stage[rel] = make_uint2((uint32_t)col, __float_as_uint(l));
+            stage[(uint32_t)rel & (uint32_t)STAGE_CAP] = make_uint2((uint32_t)col, __float_as_uint(l));
             return;
         }
         if (want_b) wepl = fmaf(l, x[col], wepl);
@@ -423,7 +467,7 @@ struct RowOut {
                     v[u] = e < n ? stage[e] : make_uint2(0u, 0u);
                 }
 #pragma unroll
-                for (int u = 0; u < U; ++u) xv[u] = x[v[u].x];
+                for (int u = 0; u < U; ++u) xv[u] = v[u].x < nvox ? x[v[u].x] : 0.f;
 #pragma unroll
                 for (int u = 0; u < U; ++u) wepl = fmaf(__uint_as_float(v[u].y), xv[u], wepl);
             }
@@ -561,9 +605,12 @@ __device__ __forceinline__ int32_t col_at(const int32_t stride[3], const int I[3
 template <typename R, int DIM, typename TW>
 __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int kind, RowOut<TW> &out, int lane,
                                          int64_t &n_entries) {
-    const int M0 = w.ray[0].M;
-    const int Ns = (kind == 2) ? w.spl.N : 0;
-    const int M1 = (kind == 2) ? w.ray[1].M : 0;
+    // item counts as the count pass writes them; the bounds only matter for a
+    // description it did not write (the walk then stays finite and the count check fails)
+    const int mmax = J.nmax + 1;
+    const int M0 = min(max(w.ray[0].M, 0), mmax);
+    const int Ns = (kind == 2) ? min(max(w.spl.N, 0), (1 << 22) + 1) : 0;
+    const int M1 = (kind == 2) ? min(max(w.ray[1].M, 0), mmax) : 0;
     const int T = M0 + Ns + M1;
     n_entries = 0;
     if (T == 0) return;
@@ -581,16 +628,16 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
     int base = 0;
     const bool spl = lane >= L0 && lane < L0 + Ls;
     if (lane < L0) {
-        lane_ray<R, DIM>(w.ray[0], P);
+        lane_ray<R, DIM>(J, w.ray[0], P);
         base = lane * K;
     } else if (spl) {
         lane_spline<R, DIM>(J, w.spl, P);
         base = (lane - L0) * K;
     } else {
-        lane_ray<R, DIM>(w.ray[1], P);
+        lane_ray<R, DIM>(J, w.ray[1], P);
         base = (lane - L0 - Ls) * K;
-        if (lane > last_lane) P.M = 0;
     }
+    P.M = (lane < L0) ? M0 : (spl ? Ns : (lane <= last_lane ? M1 : 0));
     const int first = base;
     const int last = (base + K < P.M) ? base + K : P.M;   // items [first, last)
     const int32_t stride[3] = {1, J.n[0], J.n[0] * J.n[1]};
@@ -634,11 +681,9 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
     wk.cur = col_at<DIM>(stride, Is);
     const int32_t col_start = wk.cur;
     auto close = [&](bool ok, int32_t col, float len) {
-        if (ok) {
-            if (wk.done == 0) wk.head = len;
-            else out.put(Pc + wk.done, col, len);
-            ++wk.done;
-        }
+        wk.head = (ok && wk.done == 0) ? len : wk.head;
+        out.put_if(ok && wk.done != 0, Pc + wk.done, col, len);
+        wk.done += ok ? 1 : 0;
     };
     {
         int Ip[3] = {Is[0], Is[1], Is[2]};
@@ -667,13 +712,16 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
         }
     }
 
+    // every lane must have closed exactly the crossings it counted in pass 1
+    const bool lane_ok = wk.done == c;
+
     // stitch: the entry open at a lane's start gets the tail of the last lane with a
     // crossing before it, the whole lengths of the lanes in between, and this lane's head
     const bool f = c > 0;
     int fs = f ? 1 : 0;
     float vs = wk.pend;
     wave_seg_scan(vs, fs);
-    float Oin = __shfl_up(vs, 1u, WAVE);   // open length before this lane
+    float Oin = lane_prev(vs);   // open length before this lane
     if (lane == 0) Oin = 0.f;
     if (f) out.put(Pc, col_start, Oin + wk.head);
     const float Oend = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, vs), last_lane));
@@ -681,6 +729,7 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
     if (lane == 0) out.put(ctot, ocol, Oend);
     if (out.staged) out.flush(ctot + 1, lane);
     out.fold();
+    out.bad |= !lane_ok;
     n_entries = (int64_t)ctot + 1;
 }
 
@@ -817,16 +866,21 @@ __device__ __forceinline__ int64_t count_row(const JobDev &J, const RowV<R> &w, 
     return any ? c + 1 : 0;
 }
 
-// Emit pass over rows [r0, r0 + 64) of job J by one wavefront.
+// Emit pass over rows [r0, r0 + nr) of job J by one wavefront.
 template <typename R, int DIM, bool STORE>
 __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *__restrict__ rows, int64_t r0,
-                                               int lane, uint2 *stage, int32_t *status) {
+                                               int nr, int lane, uint2 *stage, int32_t *status) {
     using TW = typename std::conditional<std::is_same<R, double>::value, double, float>::type;
-    const int64_t rend = (r0 + WAVE < J.row_count) ? r0 + WAVE : J.row_count;
+    const int64_t rend = (r0 + nr < J.row_count) ? r0 + nr : J.row_count;
+    bool bad = false;
     for (int64_t r = r0; r < rend; ++r) {
         const RowV<R> &w = rows[r];
         const int kind = w.kind;
         if (kind == 3) continue;   // walked by the per-lane kernel
+        if (kind < 0 || kind > 3) {   // not a description of the count pass
+            if (lane == 0) set_status_dev(status, PCT_EINTERNAL);
+            continue;
+        }
         RowOut<TW> out;
         out.x = J.x;
         out.wepl = 0.f;
@@ -834,7 +888,9 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *_
         out.half = (J.val_dtype == PCT_F16);
         out.want_b = (J.b != nullptr);
         out.store = STORE;
+        out.bad = false;
         out.stage = stage;
+        out.nvox = (uint32_t)J.n[0] * (uint32_t)J.n[1] * (uint32_t)(DIM == 3 ? J.n[2] : 1);
         out.staged = false;
         out.len = 0;
         int64_t pos = 0;
@@ -854,12 +910,14 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *_
         out.vf = (float *)J.vals + pos;
         int64_t ne = 0;
         if (kind != 0) wave_row<R, DIM, TW>(J, w, kind, out, lane, ne);
+        bad |= out.bad;
         if (out.store && ne != out.len && lane == 0) set_status_dev(status, PCT_EINTERNAL);
         if (out.want_b) {
             const TW bs = (TW)wave_sum((double)out.wacc);
             if (lane == 0) J.b[r] = (float)(bs * (TW)w.bfac);
         }
     }
+    if (__builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) set_status_dev(status, PCT_EINTERNAL);
 }
 
 // Rows whose spline may leave the box (kind 3): one lane per row, general walk.

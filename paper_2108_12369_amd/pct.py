@@ -21,6 +21,7 @@ PCT_STRAIGHT, PCT_HERMITE = 0, 1
 PCT_F32, PCT_F16 = 0, 1
 PCT_MIXED, PCT_PLAIN_F32 = 0, 1
 PCT_MAX_REGIONS = 16
+PCT_ORDER_GIVEN, PCT_ORDER_LPT = 0, 1
 
 SHAPES = {"ellipse": PCT_ELLIPSE, "ellipsoid": PCT_ELLIPSOID}
 VOXELIZE = {"corner_avg": PCT_CORNER_AVG, "center": PCT_CENTER}
@@ -29,7 +30,8 @@ VAL_DTYPES = {"f32": PCT_F32, "f16": PCT_F16}
 PRECISIONS = {"mixed": PCT_MIXED, "plain_f32": PCT_PLAIN_F32}
 
 SYMBOLS = ("pct_status_string", "pct_version", "pct_phantom_build", "pct_workspace_bytes",
-           "pct_count_rows", "pct_emit_csr", "pct_wepl", "pct_device_status")
+           "pct_count_rows", "pct_emit_csr", "pct_wepl", "pct_device_status", "pct_set_launch_config",
+           "pct_get_launch_config", "pct_autotune", "pct_graph_create", "pct_graph_launch", "pct_graph_destroy")
 
 
 class PctError(RuntimeError):
@@ -65,6 +67,10 @@ class Job(C.Structure):
                 ("precision", C.c_int32)]
 
 
+class LaunchConfig(C.Structure):
+    _fields_ = [("rows_per_wave", C.c_int32), ("order", C.c_int32)]
+
+
 _lib = None
 
 
@@ -89,6 +95,20 @@ def lib():
         L.pct_count_rows.restype = C.c_int32
         L.pct_device_status.argtypes = [C.c_void_p, C.c_void_p]
         L.pct_device_status.restype = C.c_int32
+        L.pct_set_launch_config.argtypes = [C.POINTER(LaunchConfig)]
+        L.pct_set_launch_config.restype = C.c_int32
+        L.pct_get_launch_config.argtypes = [C.POINTER(LaunchConfig)]
+        L.pct_get_launch_config.restype = C.c_int32
+        L.pct_autotune.argtypes = [C.c_int32, C.POINTER(Job), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                   C.POINTER(LaunchConfig)]
+        L.pct_autotune.restype = C.c_int32
+        L.pct_graph_create.argtypes = [C.c_int32, C.POINTER(Job), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                       C.POINTER(C.c_void_p)]
+        L.pct_graph_create.restype = C.c_int32
+        L.pct_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
+        L.pct_graph_launch.restype = C.c_int32
+        L.pct_graph_destroy.argtypes = [C.c_void_p]
+        L.pct_graph_destroy.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -232,6 +252,63 @@ def wepl(jobs: JobSet, ws: torch.Tensor, stream=None):
 
 def device_status(ws: torch.Tensor, stream=None) -> int:
     return int(lib().pct_device_status(_ptr(ws), _stream_ptr(stream)))
+
+
+ORDERS = {"given": PCT_ORDER_GIVEN, "lpt": PCT_ORDER_LPT}
+
+
+def set_launch_config(rows_per_wave: int | None = None, order: str | None = None):
+    """pct_set_launch_config; no arguments resets the default."""
+    if rows_per_wave is None and order is None:
+        _check(lib().pct_set_launch_config(None), "pct_set_launch_config")
+        return
+    cur = get_launch_config()
+    c = LaunchConfig(int(rows_per_wave if rows_per_wave is not None else cur["rows_per_wave"]),
+                     ORDERS[order] if order is not None else ORDERS[cur["order"]])
+    _check(lib().pct_set_launch_config(C.byref(c)), "pct_set_launch_config")
+
+
+def get_launch_config() -> dict:
+    c = LaunchConfig()
+    _check(lib().pct_get_launch_config(C.byref(c)), "pct_get_launch_config")
+    inv = {v: k for k, v in ORDERS.items()}
+    return {"rows_per_wave": int(c.rows_per_wave), "order": inv[int(c.order)]}
+
+
+def autotune(jobs: JobSet, ws: torch.Tensor, nnz_total: torch.Tensor, stream=None) -> dict:
+    """pct_autotune: picks (and sets) the fastest launch configuration for these jobs."""
+    n, arr = jobs.array()
+    c = LaunchConfig()
+    _check(lib().pct_autotune(n, arr, _ptr(ws), ws.numel(), _ptr(nnz_total), _stream_ptr(stream), C.byref(c)),
+           "pct_autotune")
+    inv = {v: k for k, v in ORDERS.items()}
+    return {"rows_per_wave": int(c.rows_per_wave), "order": inv[int(c.order)]}
+
+
+class Graph:
+    """pct_graph_create / pct_graph_launch / pct_graph_destroy for one job set."""
+
+    def __init__(self, jobs: JobSet, ws: torch.Tensor, nnz_total: torch.Tensor, build_x: bool = True):
+        self._jobs, self._ws, self._nnz = jobs, ws, nnz_total   # the graph refers to their memory
+        n, arr = jobs.array()
+        h = C.c_void_p()
+        _check(lib().pct_graph_create(n, arr, 1 if build_x else 0, _ptr(ws), ws.numel(), _ptr(nnz_total),
+                                      C.byref(h)), "pct_graph_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().pct_graph_launch(self._h, _stream_ptr(stream)), "pct_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pct_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ convenience
