@@ -131,7 +131,7 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
 }
 
 // Count pass (one lane per row): describe the row's path in the workspace and count its
-// CSR entries.  With COUNT false only the descriptions are written (WEPL-only calls).
+// CSR entries.  With COUNT false the counts are not stored (WEPL-only calls).
 template <typename R, bool COUNT>
 __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs, int n_jobs,
                                                 int32_t *__restrict__ counts, int64_t *__restrict__ tile_sums,
@@ -147,10 +147,9 @@ __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs,
         const int64_t g = J.row_begin + r;
         if (J.dim == 3) setup_row<R, 3>(J, g, w);
         else setup_row<R, 2>(J, g, w);
-        if (COUNT) {
-            cnt = (J.dim == 3) ? count_row<R, 3>(J, w, g) : count_row<R, 2>(J, w, g);
-            counts[J.count_off + r] = (int32_t)cnt;
-        }
+        // counted in both forms: the count decides which rows the per-lane walk takes
+        cnt = (J.dim == 3) ? count_row<R, 3>(J, w, g) : count_row<R, 2>(J, w, g);
+        if (COUNT) counts[J.count_off + r] = (int32_t)cnt;
     }
     if (COUNT) {
         const int64_t tot = block_sum_i64(cnt, red);

@@ -62,7 +62,7 @@ struct SplP {
 template <typename R>
 struct RowV {
     int32_t kind;           // 0: no entry, 1: one ray, 2: ray + spline + ray, 3: per-lane walk
-    int32_t pad_;
+    int32_t fast;           // every item crosses each axis at most once
     double bfac;            // WEPL noise factor 1 + r z
     RayP<R> ray[2];         // ray[0]: the straight path, or the ray into the entry point
     SplP<R> spl;
@@ -406,11 +406,11 @@ __device__ __forceinline__ float lane_prev(float v) {
 // a mask); a block of four waves uses 32 KiB.
 constexpr int STAGE_CAP = 1023;
 
-// Output of one row: entries at row-relative indices [0, len) of the row's slices of
-// cols / vals.  A row of at most STAGE_CAP entries is staged in the wave's LDS slice and
-// written out afterwards in order, 64 consecutive entries per store instruction, with
-// the x gathers for b batched there; a longer row is written directly from the walk.
-// WEPL partial per lane in FP32 over the lane's entries, folded into TW.
+// Output of one row: the row's entries are staged in the wave's LDS slice (at most
+// STAGE_CAP; longer rows are walked by the per-lane kernel) and written out afterwards
+// in order, 64 consecutive entries per store instruction, into the row's slices of
+// cols / vals, with the x gathers for b batched there.  WEPL partial per lane in FP32
+// over the lane's entries, folded into TW.
 template <typename TW>
 struct RowOut {
     int32_t *cols;
@@ -422,32 +422,12 @@ struct RowOut {
     int32_t len;
     float wepl;
     TW wacc;
-    bool store, half, want_b, staged;
+    bool store, half, want_b;
     bool bad;       // a lane closed another number of entries than it counted
 
-    // Entry `rel` if `ok`.  A staged row writes slot `rel` on every lane without a
-    // branch: a lane without an entry writes the slot of its next entry, which a later
-    // store of the wave (this lane's next entry, the head of the next lane with a
-    // crossing, or the row's last entry) overwrites in program order.
-    __device__ __forceinline__ void put_if(bool ok, int32_t rel, int32_t col, float l) {
-        if (staged) {
-            // the mask keeps even an inconsistent row inside the wave's own slice
-            stage[(uint32_t)rel & (uint32_t)STAGE_CAP] = make_uint2((uint32_t)col, __float_as_uint(l));
-            return;
-        }
-        if (ok) put(rel, col, l);
-    }
+    // Entry `rel`.  The mask keeps even an inconsistent row inside the wave's slice.
     __device__ __forceinline__ void put(int32_t rel, int32_t col, float l) {
-        if (staged) {
-            stage[(uint32_t)rel & (uint32_t)STAGE_CAP] = make_uint2((uint32_t)col, __float_as_uint(l));
-            return;
-        }
-        if (want_b) wepl = fmaf(l, x[col], wepl);
-        if (store && rel < len) {
-            cols[rel] = col;
-            if (half) vh[rel] = __float2half_rn(l);
-            else vf[rel] = l;
-        }
+        stage[(uint32_t)rel & (uint32_t)STAGE_CAP] = make_uint2((uint32_t)col, __float_as_uint(l));
     }
     __device__ __forceinline__ void fold() {
         wacc += (TW)wepl;
@@ -455,6 +435,7 @@ struct RowOut {
     }
     // Write the n staged entries and add their share of b.
     __device__ __forceinline__ void flush(int n, int lane) {
+        n = n < STAGE_CAP + 1 ? n : STAGE_CAP + 1;
         __builtin_amdgcn_wave_barrier();
         if (want_b) {
             constexpr int U = 4;
@@ -511,8 +492,8 @@ __device__ __forceinline__ void item_fast(const float hf[3], const int32_t strid
         const float dm = dff * hf[d];
         dn2 = fmaf(dm, dm, dn2);
         const bool up = di > 0;
-        const float dist = (float)(up ? R(1) - frp[d] : frp[d]);
-        lam[d] = di != 0 ? dist * __builtin_amdgcn_rcpf(fabsf(dff)) : 2.f;
+        const float dist = (float)(frp[d] - (up ? R(1) : R(0)));   // minus the distance when up
+        lam[d] = di != 0 ? fabsf(dist) * __builtin_amdgcn_rcpf(fabsf(dff)) : 2.f;
         dcol[d] = up ? stride[d] : -stride[d];
         tot += di != 0 ? 1 : 0;
     }
@@ -602,7 +583,8 @@ __device__ __forceinline__ int32_t col_at(const int32_t stride[3], const int I[3
 }
 
 // Walk one row with the whole wave; n_entries = entries produced.
-template <typename R, int DIM, typename TW>
+// FAST: every item crosses each axis at most once (the row's `fast` flag).
+template <typename R, int DIM, typename TW, bool FAST>
 __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int kind, RowOut<TW> &out, int lane,
                                          int64_t &n_entries) {
     // item counts as the count pass writes them; the bounds only matter for a
@@ -671,7 +653,6 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
     }
     int ctot;
     const int Pc = wave_excl_scan(c, ctot);
-    out.staged = out.stage != nullptr && ctot < STAGE_CAP;
 
     // pass 2: the pieces of every item
     Walker wk;
@@ -680,9 +661,13 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
     wk.done = 0;
     wk.cur = col_at<DIM>(stride, Is);
     const int32_t col_start = wk.cur;
+    // every lane stores on every call, without a branch: a lane without an entry here
+    // writes the slot of its next entry, which a later store of the wave (this lane's
+    // next entry, the head of the next lane with a crossing, or the row's last entry)
+    // overwrites in program order
     auto close = [&](bool ok, int32_t col, float len) {
         wk.head = (ok && wk.done == 0) ? len : wk.head;
-        out.put_if(ok && wk.done != 0, Pc + wk.done, col, len);
+        out.put(Pc + wk.done, col, len);
         wk.done += ok ? 1 : 0;
     };
     {
@@ -697,11 +682,15 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
                 int Ie[3];
                 piece_next<R, DIM>(P, m, mf, Fe);
                 piece_voxel<R, DIM>(P, Fe, Ie, fre);
-                bool one = true;
+                if (FAST) {
+                    item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+                } else {
+                    bool one = true;
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) one = one && (Ie[d] - Ip[d] <= 1) && (Ip[d] - Ie[d] <= 1);
-                if (one) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
-                else item_general<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+                    for (int d = 0; d < DIM; ++d) one = one && (Ie[d] - Ip[d] <= 1) && (Ip[d] - Ie[d] <= 1);
+                    if (one) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+                    else item_general<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+                }
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     Ip[d] = Ie[d];
@@ -727,7 +716,7 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
     const float Oend = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, vs), last_lane));
     const int32_t ocol = __builtin_amdgcn_readlane(wk.cur, last_lane);
     if (lane == 0) out.put(ctot, ocol, Oend);
-    if (out.staged) out.flush(ctot + 1, lane);
+    out.flush(ctot + 1, lane);
     out.fold();
     out.bad |= !lane_ok;
     n_entries = (int64_t)ctot + 1;
@@ -743,6 +732,23 @@ __device__ __forceinline__ bool hull_inside(const JobDev &J, const R p[3]) {
     return ok;
 }
 
+// Largest |F'(m)| = |c1 + 2 c2 m + 3 c3 m^2| over [0, N]: at an end or at the vertex.
+template <typename R>
+__device__ __forceinline__ R spline_max_rate(R c1, R c2, R c3, int N) {
+    const R qa = R(3) * c3, qb = R(2) * c2, n = R(N);
+    const R g0 = c1;
+    const R g1 = r_fma<R>(r_fma<R>(qa, n, qb), n, c1);
+    R g = r_fmax<R>(g0 < R(0) ? -g0 : g0, g1 < R(0) ? -g1 : g1);
+    if (qa != R(0)) {
+        const R mv = -qb / (R(2) * qa);
+        if (mv > R(0) && mv < n) {
+            const R gv = r_fma<R>(r_fma<R>(qa, mv, qb), mv, c1);
+            g = r_fmax<R>(g, gv < R(0) ? -gv : gv);
+        }
+    }
+    return g;
+}
+
 template <typename R, int DIM>
 __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowV<R> &w) {
     PathGeom<R> p;
@@ -751,6 +757,7 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowV<R> &w
     const R ninf = -r_inf<R>(), pinf = r_inf<R>();
     w.spl.N = 0;
     w.ray[1].M = 0;
+    w.fast = 1;   // a ray item crosses the dominant axis once and every other axis at most once
     if (!p.curved) {
         R lo = ninf, hi = pinf;
         const bool hit = clip_box<R, DIM>(J, p.Q, p.u, lo, hi);
@@ -789,6 +796,8 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowV<R> &w
                 w.spl.c3[d] = p.c3[d] * ih * iN3;
                 if (d < DIM) {
                     spline_windows<R>(w.spl.c1[d], w.spl.c2[d], w.spl.c3[d], p.N, thr, w.spl.win[d]);
+                    // a chord moves less than one voxel along d when |F'| < 1 over [0, N]
+                    if (!(spline_max_rate<R>(w.spl.c1[d], w.spl.c2[d], w.spl.c3[d], p.N) < R(0.999))) w.fast = 0;
                 } else {
                     w.spl.win[d][0] = w.spl.win[d][1] = w.spl.win[d][2] = w.spl.win[d][3] = -1;
                 }
@@ -839,9 +848,10 @@ __device__ __forceinline__ int64_t spline_crossings(const JobDev &J, const SplP<
 }
 
 // Number of CSR entries of a row described by w (one lane): 1 + the face crossings of
-// its items, exactly as wave_row produces them; the per-lane walk for kind 3.
+// its items, exactly as wave_row produces them; the per-lane walk for kind 3.  A row
+// with more entries than a wave stages becomes kind 3 here.
 template <typename R, int DIM>
-__device__ __forceinline__ int64_t count_row(const JobDev &J, const RowV<R> &w, int64_t g) {
+__device__ __forceinline__ int64_t count_row(const JobDev &J, RowV<R> &w, int64_t g) {
     if (w.kind == 0) return 0;
     if (w.kind == 3) {
         CountSink s;
@@ -863,7 +873,15 @@ __device__ __forceinline__ int64_t count_row(const JobDev &J, const RowV<R> &w, 
             for (int d = 0; d < DIM; ++d) c += w.ray[1].hi[d] - w.ray[1].lo[d];
         }
     }
-    return any ? c + 1 : 0;
+    const int64_t n = any ? c + 1 : 0;
+    if (n > STAGE_CAP) {
+        // more entries than the wave's LDS slice holds: the per-lane walk takes the row
+        w.kind = 3;
+        CountSink s;
+        trace_row<R, DIM, true>(J, g, s);
+        return s.n;
+    }
+    return n;
 }
 
 // Emit pass over rows [r0, r0 + nr) of job J by one wavefront.
@@ -891,7 +909,6 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *_
         out.bad = false;
         out.stage = stage;
         out.nvox = (uint32_t)J.n[0] * (uint32_t)J.n[1] * (uint32_t)(DIM == 3 ? J.n[2] : 1);
-        out.staged = false;
         out.len = 0;
         int64_t pos = 0;
         if (STORE) {
@@ -909,7 +926,10 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *_
         out.vh = (__half *)J.vals + pos;
         out.vf = (float *)J.vals + pos;
         int64_t ne = 0;
-        if (kind != 0) wave_row<R, DIM, TW>(J, w, kind, out, lane, ne);
+        if (kind != 0) {
+            if (w.fast) wave_row<R, DIM, TW, true>(J, w, kind, out, lane, ne);
+            else wave_row<R, DIM, TW, false>(J, w, kind, out, lane, ne);
+        }
         bad |= out.bad;
         if (out.store && ne != out.len && lane == 0) set_status_dev(status, PCT_EINTERNAL);
         if (out.want_b) {
