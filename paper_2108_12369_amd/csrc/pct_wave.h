@@ -77,8 +77,10 @@ template <typename R> __device__ __forceinline__ R r_fmin(R a, R b) {
 
 // ---------------------------------------------------------------- row description
 // The part of A + l D (l in [lo, hi], already clipped to the box) as a ray piece.
+// Returns false when a minor axis moves (almost) as fast as the dominant one: an item
+// could then cross it twice through rounding.
 template <typename R, int DIM>
-__device__ __forceinline__ void make_ray(const JobDev &J, const R A[3], const R D[3], R lo, R hi, bool hit,
+__device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R D[3], R lo, R hi, bool hit,
                                          RayP<R> &r) {
     R Av[3] = {R(0), R(0), R(0)}, Dv[3] = {R(0), R(0), R(0)};
     int is[3] = {0, 0, 0}, ie[3] = {0, 0, 0};
@@ -119,6 +121,7 @@ __device__ __forceinline__ void make_ray(const JobDev &J, const R A[3], const R 
     const int sdom = ied >= isd ? 1 : -1;
     // face of item end m: isd + m (upwards) or isd + 1 - m (downwards)
     const R c0d = R(sdom > 0 ? isd : isd + 1), c1d = R(sdom);
+    bool one = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         r.c0[d] = R(0);
@@ -135,10 +138,12 @@ __device__ __forceinline__ void make_ray(const JobDev &J, const R A[3], const R 
                 const R rd = Dv[d] / dvd;
                 r.c0[d] = r_fma<R>(c0d - avd, rd, Av[d]);
                 r.c1[d] = c1d * rd;
+                if (!((rd < R(0) ? -rd : rd) < R(0.999))) one = false;
             }
         }
     }
     r.M = hit ? abs(ied - isd) + 1 : 0;
+    return one;
 }
 
 // Sample ranges of one spline coordinate F(m) where consecutive computed samples may
@@ -409,16 +414,21 @@ constexpr int STAGE_CAP = 1023;
 // Output of one row: the row's entries are staged in the wave's LDS slice (at most
 // STAGE_CAP; longer rows are walked by the per-lane kernel) and written out afterwards
 // in order, 64 consecutive entries per store instruction, into the row's slices of
-// cols / vals, with the x gathers for b batched there.  WEPL partial per lane in FP32
-// over the lane's entries, folded into TW.
+// cols / vals.  WEPL partial per lane in FP32 over the lane's pieces, folded into TW.
+// Pointers into device memory in the global address space: loads and stores become
+// global_* instructions, counted by vmcnt only (a generic pointer gives flat_*
+// instructions, which every wait for a scalar or LDS access also waits for).
+#define PCT_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ PCT_GLOBAL T *gptr(T *p) { return (PCT_GLOBAL T *)p; }
+
 template <typename TW>
 struct RowOut {
-    int32_t *cols;
-    __half *vh;
-    float *vf;
-    const float *x;
+    PCT_GLOBAL int32_t *cols;
+    PCT_GLOBAL uint16_t *vh;   // binary16 bits
+    PCT_GLOBAL float *vf;
+    PCT_GLOBAL const float *x;
     uint2 *stage;   // the wave's LDS slice
-    uint32_t nvox;  // size of x: staged columns are checked against it before a gather
+    uint32_t nvox;  // size of x: every gather index is kept below it
     int32_t len;
     float wepl;
     TW wacc;
@@ -433,34 +443,34 @@ struct RowOut {
         wacc += (TW)wepl;
         wepl = 0.f;
     }
-    // Write the n staged entries and add their share of b.
+    // Write the n staged entries and add their share of b.  Lanes take consecutive
+    // entries (neighbouring voxels along the path share the cache lines of x); all
+    // gathers are issued, interleaved with the stores, before the first one is used.
     __device__ __forceinline__ void flush(int n, int lane) {
+        constexpr int U = (STAGE_CAP + 1) / WAVE;   // 16 entries per lane at most
         n = n < STAGE_CAP + 1 ? n : STAGE_CAP + 1;
+        const int m = n < len ? n : len;
         __builtin_amdgcn_wave_barrier();
-        if (want_b) {
-            constexpr int U = 4;
-            for (int e0 = 0; e0 < n; e0 += U * WAVE) {
-                uint2 v[U];
-                float xv[U];
+        float lv[U], xv[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int e = e0 + u * WAVE + lane;
-                    v[u] = e < n ? stage[e] : make_uint2(0u, 0u);
+        for (int u = 0; u < U; ++u) {
+            lv[u] = 0.f;
+            xv[u] = 0.f;
+            if (u * WAVE < n) {
+                const int e = u * WAVE + lane;
+                const uint2 v = e < n ? stage[e] : make_uint2(0u, 0u);
+                lv[u] = __uint_as_float(v.y);
+                if (want_b) xv[u] = x[v.x < nvox ? v.x : 0u];
+                if (store && e < m) {
+                    cols[e] = (int32_t)v.x;
+                    if (half) vh[e] = __half_as_ushort(__float2half_rn(lv[u]));
+                    else vf[e] = lv[u];
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u) xv[u] = v[u].x < nvox ? x[v[u].x] : 0.f;
-#pragma unroll
-                for (int u = 0; u < U; ++u) wepl = fmaf(__uint_as_float(v[u].y), xv[u], wepl);
             }
         }
-        if (store) {
-            const int m = n < len ? n : len;
-            for (int e = lane; e < m; e += WAVE) {
-                const uint2 v = stage[e];
-                cols[e] = (int32_t)v.x;
-                if (half) vh[e] = __float2half_rn(__uint_as_float(v.y));
-                else vf[e] = __uint_as_float(v.y);
-            }
+        if (want_b) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) wepl = fmaf(lv[u], xv[u], wepl);
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -516,7 +526,7 @@ __device__ __forceinline__ void item_fast(const float hf[3], const int32_t strid
         const bool go = k < tot;
         float lc = lam[k] > lp ? lam[k] : lp;
         lc = lc < 1.f ? lc : 1.f;
-        close(go, wk.cur, (k == 0 ? wk.pend : 0.f) + (lc - lp) * len);
+        close(k, go, wk.cur, (k == 0 ? wk.pend : 0.f) + (lc - lp) * len);
         wk.cur += go ? dcol[k] : 0;
         lp = go ? lc : lp;
     }
@@ -561,7 +571,7 @@ __device__ __forceinline__ void item_general(const float hf[3], const int32_t st
         float lc = (float)la;
         lc = lc > lp ? lc : lp;
         lc = lc < 1.f ? lc : 1.f;
-        close(true, wk.cur, wk.pend + (lc - lp) * len);
+        close(-1, true, wk.cur, wk.pend + (lc - lp) * len);
         wk.pend = 0.f;
         lp = lc;
 #pragma unroll
@@ -665,7 +675,12 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
     // writes the slot of its next entry, which a later store of the wave (this lane's
     // next entry, the head of the next lane with a crossing, or the row's last entry)
     // overwrites in program order
-    auto close = [&](bool ok, int32_t col, float len) {
+    // every lane stores on every call, without a branch: a lane without an entry here
+    // writes the slot of its next entry, which a later store of the wave (this lane's
+    // next entry, the head of the next lane with a crossing, or the row's last entry)
+    // overwrites in program order
+    auto close = [&](int k, bool ok, int32_t col, float len) {
+        (void)k;
         wk.head = (ok && wk.done == 0) ? len : wk.head;
         out.put(Pc + wk.done, col, len);
         wk.done += ok ? 1 : 0;
@@ -757,12 +772,12 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowV<R> &w
     const R ninf = -r_inf<R>(), pinf = r_inf<R>();
     w.spl.N = 0;
     w.ray[1].M = 0;
-    w.fast = 1;   // a ray item crosses the dominant axis once and every other axis at most once
+    w.fast = 1;   // every item crosses each axis at most once
     if (!p.curved) {
         R lo = ninf, hi = pinf;
         const bool hit = clip_box<R, DIM>(J, p.Q, p.u, lo, hi);
         w.kind = hit ? 1 : 0;
-        make_ray<R, DIM>(J, p.Q, p.u, lo, hi, hit, w.ray[0]);
+        if (!make_ray<R, DIM>(J, p.Q, p.u, lo, hi, hit, w.ray[0])) w.fast = 0;
     } else {
         // the spline lies in the convex hull of its Bezier control points
         R b1[3], b2[3];
@@ -778,11 +793,11 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowV<R> &w
         if (in) {
             R lo = ninf, hi = R(0);
             bool hit = clip_box<R, DIM>(J, p.P0, p.d0, lo, hi);
-            make_ray<R, DIM>(J, p.P0, p.d0, lo, hi, hit, w.ray[0]);
+            if (!make_ray<R, DIM>(J, p.P0, p.d0, lo, hi, hit, w.ray[0])) w.fast = 0;
             lo = R(0);
             hi = pinf;
             hit = clip_box<R, DIM>(J, p.P1, p.d1, lo, hi);
-            make_ray<R, DIM>(J, p.P1, p.d1, lo, hi, hit, w.ray[1]);
+            if (!make_ray<R, DIM>(J, p.P1, p.d1, lo, hi, hit, w.ray[1])) w.fast = 0;
             const R iN = p.invN, iN2 = iN * iN, iN3 = iN2 * iN;
             const R thr = sizeof(R) == 8 ? R(1e-9) : R(1e-2);
 #pragma unroll
@@ -900,7 +915,7 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *_
             continue;
         }
         RowOut<TW> out;
-        out.x = J.x;
+        out.x = gptr(J.x);
         out.wepl = 0.f;
         out.wacc = TW(0);
         out.half = (J.val_dtype == PCT_F16);
@@ -922,9 +937,9 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *_
                 out.len = (int32_t)(end - pos);
             }
         }
-        out.cols = J.cols + pos;
-        out.vh = (__half *)J.vals + pos;
-        out.vf = (float *)J.vals + pos;
+        out.cols = gptr(J.cols + pos);
+        out.vh = gptr((uint16_t *)J.vals + pos);
+        out.vf = gptr((float *)J.vals + pos);
         int64_t ne = 0;
         if (kind != 0) {
             if (w.fast) wave_row<R, DIM, TW, true>(J, w, kind, out, lane, ne);
