@@ -298,8 +298,10 @@ __device__ __forceinline__ void piece_next(const LaneP<R> &p, int m, R mf, R F[3
     }
 }
 
-// Voxel of a point and its position in the voxel (voxel units).  The index is kept in
-// the piece's range: the end voxels of a ray, the grid for the spline.
+// Voxel of a point and its position in that voxel (voxel units).  The index is kept in
+// the piece's range: the end voxels of a ray, the grid for the spline.  A ray's end on
+// the grid box can round to just outside it; the position is then taken in the voxel
+// the index keeps (slightly below 0 or above 1), so that the face distances stay right.
 template <typename R, int DIM>
 __device__ __forceinline__ void piece_voxel(const LaneP<R> &p, const R F[3], int I[3], R fr[3]) {
 #pragma unroll
@@ -444,33 +446,37 @@ struct RowOut {
         wepl = 0.f;
     }
     // Write the n staged entries and add their share of b.  Lanes take consecutive
-    // entries (neighbouring voxels along the path share the cache lines of x); all
-    // gathers are issued, interleaved with the stores, before the first one is used.
+    // entries (neighbouring voxels along the path share the cache lines of x); the
+    // entries go in two halves of 512, each issuing all its gathers, interleaved with
+    // its stores, before the first one is used.
     __device__ __forceinline__ void flush(int n, int lane) {
-        constexpr int U = (STAGE_CAP + 1) / WAVE;   // 16 entries per lane at most
+        constexpr int H = (STAGE_CAP + 1) / 2;   // entries per half
+        constexpr int U = H / WAVE;              // 8 per lane
         n = n < STAGE_CAP + 1 ? n : STAGE_CAP + 1;
         const int m = n < len ? n : len;
         __builtin_amdgcn_wave_barrier();
-        float lv[U], xv[U];
+        for (int h0 = 0; h0 < n; h0 += H) {
+            float lv[U], xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            lv[u] = 0.f;
-            xv[u] = 0.f;
-            if (u * WAVE < n) {
-                const int e = u * WAVE + lane;
-                const uint2 v = e < n ? stage[e] : make_uint2(0u, 0u);
-                lv[u] = __uint_as_float(v.y);
-                if (want_b) xv[u] = x[v.x < nvox ? v.x : 0u];
-                if (store && e < m) {
-                    cols[e] = (int32_t)v.x;
-                    if (half) vh[e] = __half_as_ushort(__float2half_rn(lv[u]));
-                    else vf[e] = lv[u];
+            for (int u = 0; u < U; ++u) {
+                lv[u] = 0.f;
+                xv[u] = 0.f;
+                if (h0 + u * WAVE < n) {
+                    const int e = h0 + u * WAVE + lane;
+                    const uint2 v = e < n ? stage[e] : make_uint2(0u, 0u);
+                    lv[u] = __uint_as_float(v.y);
+                    if (want_b) xv[u] = x[v.x < nvox ? v.x : 0u];
+                    if (store && e < m) {
+                        cols[e] = (int32_t)v.x;
+                        if (half) vh[e] = __half_as_ushort(__float2half_rn(lv[u]));
+                        else vf[e] = lv[u];
+                    }
                 }
             }
-        }
-        if (want_b) {
+            if (want_b) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) wepl = fmaf(lv[u], xv[u], wepl);
+                for (int u = 0; u < U; ++u) wepl = fmaf(lv[u], xv[u], wepl);
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -533,13 +539,14 @@ __device__ __forceinline__ void item_fast(const float hf[3], const int32_t strid
     wk.pend = (tot == 0 ? wk.pend : 0.f) + (1.f - lp) * len;
 }
 
-// Item with any number of crossings per axis (a chord longer than a voxel).
+// Item with any number of crossings per axis (a chord longer than a voxel).  As in the
+// fast form, distances to the faces are taken in R and the crossing parameters in FP32.
 template <typename R, int DIM, class F>
 __device__ __forceinline__ void item_general(const float hf[3], const int32_t stride[3], const int Ip[3],
                                              const R Fp[3], const R frp[3], const int Ie[3], const R Fe[3],
                                              Walker &wk, F &&close) {
     int bud[3] = {0, 0, 0}, st[3] = {1, 1, 1}, k[3] = {0, 0, 0}, tot = 0;
-    R adf[3] = {R(1), R(1), R(1)};
+    float inv[3] = {0.f, 0.f, 0.f}, d0[3] = {0.f, 0.f, 0.f};
     float dn2 = 0.f;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -547,29 +554,28 @@ __device__ __forceinline__ void item_general(const float hf[3], const int32_t st
         bud[d] = abs(dd);
         st[d] = dd > 0 ? 1 : -1;
         tot += bud[d];
-        const R df = Fe[d] - Fp[d];
-        adf[d] = df < R(0) ? -df : df;
-        const float dm = (float)df * hf[d];
+        const float dff = (float)(Fe[d] - Fp[d]);
+        inv[d] = __builtin_amdgcn_rcpf(fabsf(dff));
+        d0[d] = fabsf((float)(frp[d] - (dd > 0 ? R(1) : R(0))));   // distance to the first face
+        const float dm = dff * hf[d];
         dn2 = fmaf(dm, dm, dn2);
     }
     const float len = __builtin_amdgcn_sqrtf(dn2);
     float lp = 0.f;
     while (tot > 0) {
         int a = -1;
-        R la = R(0);
+        float la = 0.f;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             if (bud[d] > 0) {
-                const R dist = st[d] > 0 ? R(k[d] + 1) - frp[d] : frp[d] + R(k[d]);
-                const R ld = dist / adf[d];
+                const float ld = (d0[d] + (float)k[d]) * inv[d];
                 if (a < 0 || ld < la) {
                     a = d;
                     la = ld;
                 }
             }
         }
-        float lc = (float)la;
-        lc = lc > lp ? lc : lp;
+        float lc = la > lp ? la : lp;
         lc = lc < 1.f ? lc : 1.f;
         close(-1, true, wk.cur, wk.pend + (lc - lp) * len);
         wk.pend = 0.f;
@@ -697,15 +703,8 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
                 int Ie[3];
                 piece_next<R, DIM>(P, m, mf, Fe);
                 piece_voxel<R, DIM>(P, Fe, Ie, fre);
-                if (FAST) {
-                    item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
-                } else {
-                    bool one = true;
-#pragma unroll
-                    for (int d = 0; d < DIM; ++d) one = one && (Ie[d] - Ip[d] <= 1) && (Ip[d] - Ie[d] <= 1);
-                    if (one) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
-                    else item_general<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
-                }
+                if (FAST) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+                else item_general<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     Ip[d] = Ie[d];
