@@ -34,7 +34,7 @@ struct WsHeader {
 static inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t jobs_off, order_off, sums_off, offs_off, counts_off, rows_off, total;
+    size_t jobs_off, order_off, sums_off, offs_off, flags_off, counts_off, rows_off, total;
     int64_t total_tiles, total_rows;
 };
 
@@ -54,7 +54,8 @@ static Layout layout_of(int32_t n_jobs, const int64_t *row_counts) {
     L.order_off = align256(L.jobs_off + (size_t)n_jobs * sizeof(JobDev));
     L.sums_off = align256(L.order_off + (size_t)n_jobs * sizeof(int32_t));
     L.offs_off = align256(L.sums_off + (size_t)(tiles + 1) * sizeof(int64_t));
-    L.counts_off = align256(L.offs_off + (size_t)(tiles + 1) * sizeof(int64_t));
+    L.flags_off = align256(L.offs_off + (size_t)(tiles + 1) * sizeof(int64_t));
+    L.counts_off = align256(L.flags_off + (size_t)(tiles + 1) * sizeof(int32_t));
     L.rows_off = align256(L.counts_off + (size_t)rows * sizeof(int32_t));
     L.total = align256(L.rows_off + (size_t)rows * ROWW_BYTES);
     return L;
@@ -135,13 +136,14 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
 template <typename R, bool COUNT>
 __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs, int n_jobs,
                                                 int32_t *__restrict__ counts, int64_t *__restrict__ tile_sums,
-                                                RowV<R> *__restrict__ rowbuf) {
+                                                int32_t *__restrict__ tile_flags, RowV<R> *__restrict__ rowbuf) {
     __shared__ int64_t red[TILE / 64];
     const int64_t tile = blockIdx.x;
     const int jid = job_of_tile(jobs, n_jobs, tile);
     const JobDev &J = jobs[jid];
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     int64_t cnt = 0;
+    int lane_walk = 0;
     if (r < J.row_count) {
         RowV<R> &w = rowbuf[J.count_off + r];
         const int64_t g = J.row_begin + r;
@@ -150,7 +152,11 @@ __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs,
         // counted in both forms: the count decides which rows the per-lane walk takes
         cnt = (J.dim == 3) ? count_row<R, 3>(J, w, g) : count_row<R, 2>(J, w, g);
         if (COUNT) counts[J.count_off + r] = (int32_t)cnt;
+        lane_walk = (w.kind == 3) ? 1 : 0;
     }
+    // whether the per-lane emit kernel has a row in this tile
+    const int any_lane = __syncthreads_or(lane_walk);
+    if (threadIdx.x == 0) tile_flags[tile] = any_lane;
     if (COUNT) {
         const int64_t tot = block_sum_i64(cnt, red);
         if (threadIdx.x == 0) tile_sums[tile] = tot;
@@ -240,8 +246,10 @@ __global__ void __launch_bounds__(TILE) k_emit_wave(const JobDev *__restrict__ j
 template <typename R, bool STORE>
 __global__ void __launch_bounds__(TILE) k_emit_lane(const JobDev *__restrict__ jobs, int n_jobs,
                                                     const RowV<R> *__restrict__ rowbuf,
+                                                    const int32_t *__restrict__ tile_flags,
                                                     int32_t *__restrict__ status) {
     const int64_t tile = blockIdx.x;
+    if (tile_flags[tile] == 0) return;   // no row of this tile needs the per-lane walk
     const int jid = job_of_tile(jobs, n_jobs, tile);
     const JobDev &J = jobs[jid];
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
@@ -601,10 +609,10 @@ pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
     if (T > 0) {
         if (jobs[0].precision == PCT_MIXED)
             hipLaunchKernelGGL((k_count<double, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums,
-                               (RowV<double> *)(w + P.L.rows_off));
+                               (int32_t *)(w + P.L.flags_off), (RowV<double> *)(w + P.L.rows_off));
         else
             hipLaunchKernelGGL((k_count<float, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums,
-                               (RowV<float> *)(w + P.L.rows_off));
+                               (int32_t *)(w + P.L.flags_off), (RowV<float> *)(w + P.L.rows_off));
     }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_THREADS), 0, s, J, n_jobs, T, sums, offs, nnz_total_dev);
     if (T > 0) hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, offs);
@@ -633,31 +641,32 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
         (jobs[j].phantom->dim == 3 ? has3 : has2) = true;
     }
     const int32_t *eorder = (const int32_t *)(w + P.L.order_off);
+    int32_t *flags = (int32_t *)(w + P.L.flags_off);
     void *rows = w + P.L.rows_off;
     const dim3 grid((unsigned)T), egrid((unsigned)P.total_etiles), block(TILE);
     if (mixed) {
         RowV<double> *rb = (RowV<double> *)rows;
-        if (!store) hipLaunchKernelGGL((k_count<double, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, rb);
+        if (!store) hipLaunchKernelGGL((k_count<double, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, flags, rb);
         if (store) {
             if (has2) hipLaunchKernelGGL((k_emit_wave<double, true, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
             if (has3) hipLaunchKernelGGL((k_emit_wave<double, true, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            hipLaunchKernelGGL((k_emit_lane<double, true>), grid, block, 0, s, J, n_jobs, rb, status);
+            hipLaunchKernelGGL((k_emit_lane<double, true>), grid, block, 0, s, J, n_jobs, rb, flags, status);
         } else {
             if (has2) hipLaunchKernelGGL((k_emit_wave<double, false, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
             if (has3) hipLaunchKernelGGL((k_emit_wave<double, false, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            hipLaunchKernelGGL((k_emit_lane<double, false>), grid, block, 0, s, J, n_jobs, rb, status);
+            hipLaunchKernelGGL((k_emit_lane<double, false>), grid, block, 0, s, J, n_jobs, rb, flags, status);
         }
     } else {
         RowV<float> *rb = (RowV<float> *)rows;
-        if (!store) hipLaunchKernelGGL((k_count<float, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, rb);
+        if (!store) hipLaunchKernelGGL((k_count<float, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, flags, rb);
         if (store) {
             if (has2) hipLaunchKernelGGL((k_emit_wave<float, true, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
             if (has3) hipLaunchKernelGGL((k_emit_wave<float, true, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            hipLaunchKernelGGL((k_emit_lane<float, true>), grid, block, 0, s, J, n_jobs, rb, status);
+            hipLaunchKernelGGL((k_emit_lane<float, true>), grid, block, 0, s, J, n_jobs, rb, flags, status);
         } else {
             if (has2) hipLaunchKernelGGL((k_emit_wave<float, false, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
             if (has3) hipLaunchKernelGGL((k_emit_wave<float, false, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            hipLaunchKernelGGL((k_emit_lane<float, false>), grid, block, 0, s, J, n_jobs, rb, status);
+            hipLaunchKernelGGL((k_emit_lane<float, false>), grid, block, 0, s, J, n_jobs, rb, flags, status);
         }
     }
     return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
