@@ -907,6 +907,11 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *_
     bool bad = false;
     for (int64_t r = r0; r < rend; ++r) {
         const RowV<R> &w = rows[r];
+        // start fetching the next row's description (8 B per lane): it is in cache when
+        // the lanes load their pieces of it
+        uint2 next = make_uint2(0u, 0u);
+        constexpr int NW = (int)((sizeof(RowV<R>) + 7) / 8);
+        if (r + 1 < rend && lane < NW) next = reinterpret_cast<const uint2 *>(rows + r + 1)[lane];
         const int kind = w.kind;
         if (kind == 3) continue;   // walked by the per-lane kernel
         if (kind < 0 || kind > 3) {   // not a description of the count pass
@@ -950,6 +955,7 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *_
             const TW bs = (TW)wave_sum((double)out.wacc);
             if (lane == 0) J.b[r] = (float)(bs * (TW)w.bfac);
         }
+        asm volatile("" ::"v"(next.x), "v"(next.y));   // keeps the fetch; waits for it only here
     }
     if (__builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) set_status_dev(status, PCT_EINTERNAL);
 }
