@@ -907,11 +907,11 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *_
     bool bad = false;
     for (int64_t r = r0; r < rend; ++r) {
         const RowV<R> &w = rows[r];
-        // start fetching the next row's description (8 B per lane): it is in cache when
-        // the lanes load their pieces of it
+        // start fetching the description of the row after next (8 B per lane): it is in
+        // cache when the lanes load their pieces of it
         uint2 next = make_uint2(0u, 0u);
         constexpr int NW = (int)((sizeof(RowV<R>) + 7) / 8);
-        if (r + 1 < rend && lane < NW) next = reinterpret_cast<const uint2 *>(rows + r + 1)[lane];
+        if (r + 2 < rend && lane < NW) next = reinterpret_cast<const uint2 *>(rows + r + 2)[lane];
         const int kind = w.kind;
         if (kind == 3) continue;   // walked by the per-lane kernel
         if (kind < 0 || kind > 3) {   // not a description of the count pass

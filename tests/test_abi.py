@@ -198,3 +198,51 @@ def test_job_validation(P, W):
     nnz = ptr(8)
     assert P.lib().pct_count_rows(n3, arr3, ptr(need - 1), need - 1, nnz, None) == -4
     assert P.lib().pct_count_rows(n3, arr3, None, need, nnz, None) == -4
+
+
+def test_launch_config_host_side(P):
+    """pct_set/get_launch_config are host-only: valid values round-trip, others are refused
+    and leave the configuration unchanged; NULL restores the default."""
+    lib = P.lib()
+    cfg = P.LaunchConfig()
+    assert lib.pct_get_launch_config(C.byref(cfg)) == 0
+    assert lib.pct_get_launch_config(None) == -1
+    for rpw in (16, 32, 64):
+        for order in (P.PCT_ORDER_GIVEN, P.PCT_ORDER_LPT):
+            assert lib.pct_set_launch_config(C.byref(P.LaunchConfig(rpw, order))) == 0
+            got = P.LaunchConfig()
+            lib.pct_get_launch_config(C.byref(got))
+            assert (got.rows_per_wave, got.order) == (rpw, order)
+    before = P.LaunchConfig()
+    lib.pct_get_launch_config(C.byref(before))
+    for bad in ((0, 1), (48, 1), (128, 0), (64, 2), (64, -1)):
+        assert lib.pct_set_launch_config(C.byref(P.LaunchConfig(*bad))) == -1
+        now = P.LaunchConfig()
+        lib.pct_get_launch_config(C.byref(now))
+        assert (now.rows_per_wave, now.order) == (before.rows_per_wave, before.order)
+    assert lib.pct_set_launch_config(None) == 0
+    lib.pct_get_launch_config(C.byref(cfg))
+    assert (cfg.rows_per_wave, cfg.order) == (64, P.PCT_ORDER_LPT)
+
+
+def test_graph_and_autotune_validate_on_host(P, W):
+    """Both refuse bad arguments before any HIP call (no GPU needed)."""
+    lib = P.lib()
+    cfg = W.c0()
+    js = P.JobSet()
+    js.add(cfg["phantom"], cfg["beam"], None)
+    n, arr = js.array()
+    h = C.c_void_p()
+    # no row_ptr: the count pass cannot run
+    assert lib.pct_graph_create(n, arr, 0, None, 1 << 30, None, C.byref(h)) == -1
+    assert h.value is None
+    assert lib.pct_graph_create(n, arr, 0, None, 1 << 30, None, None) == -1
+    best = P.LaunchConfig()
+    assert lib.pct_autotune(n, arr, None, 1 << 30, None, None, C.byref(best)) == -1
+    assert lib.pct_autotune(n, arr, None, 1 << 30, None, None, None) == -1
+    # a bad descriptor is refused the same way
+    arr[0].val_dtype = 7
+    arr[0].row_ptr_dev = 1 << 20
+    assert lib.pct_graph_create(n, arr, 0, None, 1 << 30, C.c_void_p(1 << 20), C.byref(h)) == -1
+    assert lib.pct_graph_launch(None, None) == -1
+    assert lib.pct_graph_destroy(None) == 0
