@@ -39,7 +39,8 @@ struct Layout {
 };
 
 // per-row path descriptions (the larger of the two precisions)
-constexpr size_t ROWW_BYTES = sizeof(RowV<double>) > sizeof(RowV<float>) ? sizeof(RowV<double>) : sizeof(RowV<float>);
+constexpr size_t ROWW_BYTES = rv_bytes<double>() > rv_bytes<float>() ? rv_bytes<double>() : rv_bytes<float>();
+static_assert(TILE == RV_TILE, "descriptions are stored per count tile");
 
 static Layout layout_of(int32_t n_jobs, const int64_t *row_counts) {
     Layout L{};
@@ -57,7 +58,7 @@ static Layout layout_of(int32_t n_jobs, const int64_t *row_counts) {
     L.flags_off = align256(L.offs_off + (size_t)(tiles + 1) * sizeof(int64_t));
     L.counts_off = align256(L.flags_off + (size_t)(tiles + 1) * sizeof(int32_t));
     L.rows_off = align256(L.counts_off + (size_t)rows * sizeof(int32_t));
-    L.total = align256(L.rows_off + (size_t)rows * ROWW_BYTES);
+    L.total = align256(L.rows_off + (size_t)tiles * RV_TILE * ROWW_BYTES);   // whole tiles of descriptions
     return L;
 }
 
@@ -136,7 +137,7 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
 template <typename R, bool COUNT>
 __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs, int n_jobs,
                                                 int32_t *__restrict__ counts, int64_t *__restrict__ tile_sums,
-                                                int32_t *__restrict__ tile_flags, RowV<R> *__restrict__ rowbuf) {
+                                                int32_t *__restrict__ tile_flags, char *__restrict__ rowbuf) {
     __shared__ int64_t red[TILE / 64];
     const int64_t tile = blockIdx.x;
     const int jid = job_of_tile(jobs, n_jobs, tile);
@@ -145,14 +146,20 @@ __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs,
     int64_t cnt = 0;
     int lane_walk = 0;
     if (r < J.row_count) {
-        RowV<R> &w = rowbuf[J.count_off + r];
         const int64_t g = J.row_begin + r;
-        if (J.dim == 3) setup_row<R, 3>(J, g, w);
-        else setup_row<R, 2>(J, g, w);
         // counted in both forms: the count decides which rows the per-lane walk takes
-        cnt = (J.dim == 3) ? count_row<R, 3>(J, w, g) : count_row<R, 2>(J, w, g);
+        if (J.dim == 3) {
+            const RowRefD<R, 3> w = row_ref<R, 3>(rowbuf, J, r);
+            setup_row<R, 3>(J, g, w);
+            cnt = count_row<R, 3>(J, w, g);
+            lane_walk = (RV(w, kind) == 3) ? 1 : 0;
+        } else {
+            const RowRefD<R, 2> w = row_ref<R, 2>(rowbuf, J, r);
+            setup_row<R, 2>(J, g, w);
+            cnt = count_row<R, 2>(J, w, g);
+            lane_walk = (RV(w, kind) == 3) ? 1 : 0;
+        }
         if (COUNT) counts[J.count_off + r] = (int32_t)cnt;
-        lane_walk = (w.kind == 3) ? 1 : 0;
     }
     // whether the per-lane emit kernel has a row in this tile
     const int any_lane = __syncthreads_or(lane_walk);
@@ -228,7 +235,7 @@ __global__ void __launch_bounds__(TILE) k_row_ptr(const JobDev *__restrict__ job
 // other dimension return at once.  A block is one emit tile: 4 waves of rpw rows.
 template <typename R, bool STORE, int DIM>
 __global__ void __launch_bounds__(TILE) k_emit_wave(const JobDev *__restrict__ jobs, const int32_t *__restrict__ eorder,
-                                                    int n_jobs, const RowV<R> *__restrict__ rowbuf,
+                                                    int n_jobs, char *__restrict__ rowbuf,
                                                     int32_t *__restrict__ status) {
     __shared__ uint2 stage[TILE / WAVE][STAGE_CAP + 1];   // 1024 entries per wave
     const int64_t tile = blockIdx.x;
@@ -238,14 +245,13 @@ __global__ void __launch_bounds__(TILE) k_emit_wave(const JobDev *__restrict__ j
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int lane = threadIdx.x % WAVE;
     const int64_t r0 = ((tile - J.etile_base) * (TILE / WAVE) + wave) * J.rpw;
-    const RowV<R> *rows = rowbuf + J.count_off;
-    emit_rows_wave<R, DIM, STORE>(J, rows, r0, J.rpw, lane, stage[wave], status);
+    emit_rows_wave<R, DIM, STORE>(J, rowbuf, r0, J.rpw, lane, stage[wave], status);
 }
 
 // Rows whose spline may leave the grid box: one lane per row.
 template <typename R, bool STORE>
 __global__ void __launch_bounds__(TILE) k_emit_lane(const JobDev *__restrict__ jobs, int n_jobs,
-                                                    const RowV<R> *__restrict__ rowbuf,
+                                                    char *__restrict__ rowbuf,
                                                     const int32_t *__restrict__ tile_flags,
                                                     int32_t *__restrict__ status) {
     const int64_t tile = blockIdx.x;
@@ -254,10 +260,13 @@ __global__ void __launch_bounds__(TILE) k_emit_lane(const JobDev *__restrict__ j
     const JobDev &J = jobs[jid];
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     if (r >= J.row_count) return;
-    const RowV<R> &w = rowbuf[J.count_off + r];
-    if (w.kind != 3) return;
-    if (J.dim == 3) emit_row_lane<R, 3, STORE>(J, w, r, status);
-    else emit_row_lane<R, 2, STORE>(J, w, r, status);
+    if (J.dim == 3) {
+        const RowRefD<R, 3> w = row_ref<R, 3>(rowbuf, J, r);
+        if (RV(w, kind) == 3) emit_row_lane<R, 3, STORE>(J, w, r, status);
+    } else {
+        const RowRefD<R, 2> w = row_ref<R, 2>(rowbuf, J, r);
+        if (RV(w, kind) == 3) emit_row_lane<R, 2, STORE>(J, w, r, status);
+    }
 }
 
 // ---------------------------------------------------------------- phantom build
@@ -609,10 +618,10 @@ pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
     if (T > 0) {
         if (jobs[0].precision == PCT_MIXED)
             hipLaunchKernelGGL((k_count<double, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums,
-                               (int32_t *)(w + P.L.flags_off), (RowV<double> *)(w + P.L.rows_off));
+                               (int32_t *)(w + P.L.flags_off), w + P.L.rows_off);
         else
             hipLaunchKernelGGL((k_count<float, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums,
-                               (int32_t *)(w + P.L.flags_off), (RowV<float> *)(w + P.L.rows_off));
+                               (int32_t *)(w + P.L.flags_off), w + P.L.rows_off);
     }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_THREADS), 0, s, J, n_jobs, T, sums, offs, nnz_total_dev);
     if (T > 0) hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, offs);
@@ -645,7 +654,7 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
     void *rows = w + P.L.rows_off;
     const dim3 grid((unsigned)T), egrid((unsigned)P.total_etiles), block(TILE);
     if (mixed) {
-        RowV<double> *rb = (RowV<double> *)rows;
+        char *rb = (char *)rows;
         if (!store) hipLaunchKernelGGL((k_count<double, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, flags, rb);
         if (store) {
             if (has2) hipLaunchKernelGGL((k_emit_wave<double, true, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
@@ -657,7 +666,7 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
             hipLaunchKernelGGL((k_emit_lane<double, false>), grid, block, 0, s, J, n_jobs, rb, flags, status);
         }
     } else {
-        RowV<float> *rb = (RowV<float> *)rows;
+        char *rb = (char *)rows;
         if (!store) hipLaunchKernelGGL((k_count<float, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, flags, rb);
         if (store) {
             if (has2) hipLaunchKernelGGL((k_emit_wave<float, true, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);

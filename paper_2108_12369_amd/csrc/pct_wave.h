@@ -68,6 +68,46 @@ struct RowV {
     SplP<R> spl;
 };
 
+// Storage of the descriptions.  Each job has RV_TILE * rv_bytes bytes per count tile.
+// Inside it, rows are grouped by 2^S: 16-byte chunk c of row i of a group sits at byte
+// (c * 2^S + i) * 16 of the group's block.
+//   S = 8 (2D grids): chunk-transposed over a whole tile -- the count pass (one lane per
+//          row) writes every chunk of 64 consecutive rows with one contiguous 1 KiB store;
+//   S = 0 (3D grids): each row contiguous -- the emit reads a row from 4 cache lines,
+//          which need not stay cached for the following rows while the x gathers of a
+//          large 3D grid (larger than one L2) stream through the cache.
+// A field never straddles a chunk (all are 4 or 8 bytes at their natural alignment).
+constexpr int RV_TILE = 256;
+template <typename R>
+constexpr size_t rv_bytes() { return (sizeof(RowV<R>) + 15) & ~size_t(15); }
+template <int DIM>
+constexpr int rv_shift() { return DIM == 2 ? 8 : 0; }
+
+template <typename R, int S>
+struct RowRef {
+    char *tb;    // the row's group block
+    int i;       // row in the group
+    template <class T>
+    __device__ __forceinline__ T &at(size_t off) const {
+        return *reinterpret_cast<T *>(tb + ((((off >> 4) << S) + (size_t)i) << 4) + (off & 15));
+    }
+};
+template <typename R, int DIM>
+using RowRefD = RowRef<R, rv_shift<DIM>()>;
+
+// The description of row r of job J.
+template <typename R, int DIM>
+__device__ __forceinline__ RowRefD<R, DIM> row_ref(char *rowbuf, const JobDev &J, int64_t r) {
+    constexpr int S = rv_shift<DIM>();
+    char *jb = rowbuf + J.tile_base * (int64_t)(RV_TILE * rv_bytes<R>());
+    const int64_t grp = r >> S;
+    return RowRefD<R, DIM>{jb + grp * (int64_t)(rv_bytes<R>() << S), (int)(r & ((1 << S) - 1))};
+}
+
+#define RV(w, member) \
+    (w).template at<typename std::remove_reference<decltype(((RowV<R> *)nullptr)->member)>::type>( \
+        __builtin_offsetof(RowV<R>, member))
+
 template <typename R> __device__ __forceinline__ R r_fmax(R a, R b) {
     if constexpr (std::is_same<R, float>::value) return fmaxf(a, b); else return fmax(a, b);
 }
@@ -79,9 +119,9 @@ template <typename R> __device__ __forceinline__ R r_fmin(R a, R b) {
 // The part of A + l D (l in [lo, hi], already clipped to the box) as a ray piece.
 // Returns false when a minor axis moves (almost) as fast as the dominant one: an item
 // could then cross it twice through rounding.
-template <typename R, int DIM>
+template <typename R, int DIM, int WHICH>
 __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R D[3], R lo, R hi, bool hit,
-                                         RayP<R> &r) {
+                                         RowRefD<R, DIM> w) {
     R Av[3] = {R(0), R(0), R(0)}, Dv[3] = {R(0), R(0), R(0)};
     int is[3] = {0, 0, 0}, ie[3] = {0, 0, 0};
     int dom = 0;
@@ -93,8 +133,8 @@ __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R 
         Dv[d] = D[d] * ih;
         const R P = A[d] + lo * D[d];
         const R E = A[d] + hi * D[d];
-        r.fS[d] = (P - R(J.o[d])) * ih;
-        r.fE[d] = (E - R(J.o[d])) * ih;
+        RV(w, ray[WHICH].fS[d]) = (P - R(J.o[d])) * ih;
+        RV(w, ray[WHICH].fE[d]) = (E - R(J.o[d])) * ih;
         is[d] = vox_index<R>(P, J.o[d], J.invh[d], J.n[d]);
         ie[d] = vox_index<R>(E, J.o[d], J.invh[d], J.n[d]);
         const R rate = Dv[d] < R(0) ? -Dv[d] : Dv[d];
@@ -105,8 +145,8 @@ __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R 
     }
 #pragma unroll
     for (int d = DIM; d < 3; ++d) {
-        r.fS[d] = R(0);
-        r.fE[d] = R(0);
+        RV(w, ray[WHICH].fS[d]) = R(0);
+        RV(w, ray[WHICH].fE[d]) = R(0);
     }
     int isd = 0, ied = 0;
     R avd = R(0), dvd = R(1);
@@ -124,37 +164,58 @@ __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R 
     bool one = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        r.c0[d] = R(0);
-        r.c1[d] = R(0);
-        r.lo[d] = 0;
-        r.hi[d] = 0;
+        R c0 = R(0), c1 = R(0);
+        int lo_ = 0, hi_ = 0;
         if (d < DIM) {
-            r.lo[d] = is[d] < ie[d] ? is[d] : ie[d];
-            r.hi[d] = is[d] < ie[d] ? ie[d] : is[d];
+            lo_ = is[d] < ie[d] ? is[d] : ie[d];
+            hi_ = is[d] < ie[d] ? ie[d] : is[d];
             if (d == dom) {
-                r.c0[d] = c0d;
-                r.c1[d] = c1d;
+                c0 = c0d;
+                c1 = c1d;
             } else {
                 const R rd = Dv[d] / dvd;
-                r.c0[d] = r_fma<R>(c0d - avd, rd, Av[d]);
-                r.c1[d] = c1d * rd;
+                c0 = r_fma<R>(c0d - avd, rd, Av[d]);
+                c1 = c1d * rd;
                 if (!((rd < R(0) ? -rd : rd) < R(0.999))) one = false;
             }
         }
+        RV(w, ray[WHICH].c0[d]) = c0;
+        RV(w, ray[WHICH].c1[d]) = c1;
+        RV(w, ray[WHICH].lo[d]) = lo_;
+        RV(w, ray[WHICH].hi[d]) = hi_;
     }
-    r.M = hit ? abs(ied - isd) + 1 : 0;
+    RV(w, ray[WHICH].M) = hit ? abs(ied - isd) + 1 : 0;
     return one;
+}
+
+// Whether |F'(m)| = |c1 + 2 c2 m + 3 c3 m^2| stays above thr with one sign over [s0, s1]
+// (true for an empty range): the smallest |F'| is at an end or at the vertex of F'.
+template <typename R>
+__device__ __forceinline__ bool rate_ok(R qa, R qb, R qc, R mv, int s0i, int s1i, R thr) {
+    if (s1i <= s0i) return true;
+    const R s0 = R(s0i), s1 = R(s1i);
+    const R g0 = r_fma<R>(r_fma<R>(qa, s0, qb), s0, qc);
+    const R g1 = r_fma<R>(r_fma<R>(qa, s1, qb), s1, qc);
+    bool same = (g0 > R(0)) == (g1 > R(0));
+    R gmin = r_fmin<R>(g0 < R(0) ? -g0 : g0, g1 < R(0) ? -g1 : g1);
+    if (mv > s0 && mv < s1) {
+        const R gv = r_fma<R>(r_fma<R>(qa, mv, qb), mv, qc);
+        same = same && ((gv > R(0)) == (g0 > R(0)));
+        gmin = r_fmin<R>(gmin, gv < R(0) ? -gv : gv);
+    }
+    return same && gmin > thr;
 }
 
 // Sample ranges of one spline coordinate F(m) where consecutive computed samples may
 // fail to be strictly monotone: around the roots of F'(m) = c1 + 2 c2 m + 3 c3 m^2 in
 // the sampled range, and any stretch between them where |F'| (the step per chord)
 // drops below `thr` -- far above the rounding of a sample, so that outside the ranges
-// the computed samples keep the order of the exact ones.
+// the computed samples keep the order of the exact ones.  Up to two ranges [a, b]
+// (a < b; unused: -1, -1), merged conservatively.
 template <typename R>
 __device__ __forceinline__ void spline_windows(R c1, R c2, R c3, int N, R thr, int32_t win[4]) {
     const R qa = R(3) * c3, qb = R(2) * c2, qc = c1;
-    R rt[2] = {R(0), R(0)};
+    R rt0 = R(0), rt1 = R(0);
     int nr = 0;
     if (qa != R(0)) {
         const R disc = qb * qb - R(4) * qa * qc;
@@ -163,65 +224,72 @@ __device__ __forceinline__ void spline_windows(R c1, R c2, R c3, int N, R thr, i
             const R t = (qb >= R(0)) ? -(qb + sq) : (sq - qb);
             const R r1 = t / (R(2) * qa);
             const R r2 = (t != R(0)) ? (R(2) * qc) / t : r1;
-            rt[0] = r1 < r2 ? r1 : r2;
-            rt[1] = r1 < r2 ? r2 : r1;
+            rt0 = r1 < r2 ? r1 : r2;
+            rt1 = r1 < r2 ? r2 : r1;
             nr = 2;
         }
     } else if (qb != R(0)) {
-        rt[0] = -qc / qb;
+        rt0 = -qc / qb;
         nr = 1;
     }
-    // segments of [0, N] in order: interval, window, interval, window, interval
-    int a[5], b[5];
-    bool bad[5];
-    int ns = 0, prev = 0;
-    for (int i = 0; i < nr; ++i) {
-        const R r = rt[i];
-        if (!(r > R(-1) && r < R(N + 1))) continue;
-        int wa = (int)r_floor<R>(r) - 1, wb = (int)r_ceil<R>(r) + 1;
-        wa = wa < 0 ? 0 : wa;
-        wb = wb > N ? N : wb;
-        if (ns > 0 && wa <= prev) {   // overlaps the previous window: extend it
-            b[ns - 1] = wb > b[ns - 1] ? wb : b[ns - 1];
-            prev = b[ns - 1];
-            continue;
-        }
-        a[ns] = prev; b[ns] = wa; bad[ns] = false; ++ns;
-        a[ns] = wa; b[ns] = wb; bad[ns] = true; ++ns;
-        prev = wb;
+    // windows of two samples on either side of each root in (-1, N + 1)
+    bool v0 = false, v1 = false;
+    int wa0 = 0, wb0 = 0, wa1 = 0, wb1 = 0;
+    if (nr >= 1 && rt0 > R(-1) && rt0 < R(N + 1)) {
+        v0 = true;
+        wa0 = max((int)r_floor<R>(rt0) - 1, 0);
+        wb0 = min((int)r_ceil<R>(rt0) + 1, N);
     }
-    a[ns] = prev; b[ns] = N; bad[ns] = false; ++ns;
-    // intervals between windows: the smallest |F'| is at an end or at the vertex of F'
+    if (nr >= 2 && rt1 > R(-1) && rt1 < R(N + 1)) {
+        v1 = true;
+        wa1 = max((int)r_floor<R>(rt1) - 1, 0);
+        wb1 = min((int)r_ceil<R>(rt1) + 1, N);
+    }
+    if (!v0 && v1) {
+        v0 = true;
+        wa0 = wa1;
+        wb0 = wb1;
+        v1 = false;
+    }
+    if (v0 && v1 && wa1 <= wb0) {   // overlapping windows
+        wb0 = max(wb0, wb1);
+        v1 = false;
+    }
+    // segments of [0, N] in order: interval, window, interval, window, interval; an
+    // interval whose rate is too small becomes unsafe as well
     const R mv = (qa != R(0)) ? -qb / (R(2) * qa) : R(-1);
-    for (int s = 0; s < ns; ++s) {
-        if (bad[s] || b[s] <= a[s]) continue;
-        const R s0 = R(a[s]), s1 = R(b[s]);
-        const R g0 = r_fma<R>(r_fma<R>(qa, s0, qb), s0, qc);
-        const R g1 = r_fma<R>(r_fma<R>(qa, s1, qb), s1, qc);
-        bool same = (g0 > R(0)) == (g1 > R(0));
-        R gmin = r_fmin<R>(g0 < R(0) ? -g0 : g0, g1 < R(0) ? -g1 : g1);
-        if (mv > s0 && mv < s1) {
-            const R gv = r_fma<R>(r_fma<R>(qa, mv, qb), mv, qc);
-            same = same && ((gv > R(0)) == (g0 > R(0)));
-            gmin = r_fmin<R>(gmin, gv < R(0) ? -gv : gv);
-        }
-        if (!same || !(gmin > thr)) bad[s] = true;
-    }
+    const int e0 = v0 ? wa0 : N;
+    const int s1 = v0 ? wb0 : N, e1 = v1 ? wa1 : N;
+    const int s2 = v1 ? wb1 : N;
+    int sa[5] = {0, wa0, s1, wa1, s2};
+    int sb[5] = {e0, wb0, e1, wb1, N};
+    bool bad[5] = {!rate_ok<R>(qa, qb, qc, mv, 0, e0, thr), v0, v0 && !rate_ok<R>(qa, qb, qc, mv, s1, e1, thr), v1,
+                   v1 && !rate_ok<R>(qa, qb, qc, mv, s2, N, thr)};
     // merge adjacent unsafe segments; at most two ranges remain
-    int nw = 0;
-    win[0] = win[1] = win[2] = win[3] = -1;
-    for (int s = 0; s < ns; ++s) {
-        if (!bad[s] || b[s] <= a[s]) continue;
-        if (nw > 0 && win[2 * nw - 1] >= a[s]) {
-            win[2 * nw - 1] = b[s] > win[2 * nw - 1] ? b[s] : win[2 * nw - 1];
-        } else if (nw < 2) {
-            win[2 * nw] = a[s];
-            win[2 * nw + 1] = b[s];
-            ++nw;
+    int a0 = -1, b0 = -1, a1 = -1, b1 = -1, nw = 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        if (!bad[k] || sb[k] <= sa[k]) continue;
+        if (nw == 1 && b0 >= sa[k]) {
+            b0 = max(b0, sb[k]);
+        } else if (nw == 2 && b1 >= sa[k]) {
+            b1 = max(b1, sb[k]);
+        } else if (nw == 0) {
+            a0 = sa[k];
+            b0 = sb[k];
+            nw = 1;
+        } else if (nw == 1) {
+            a1 = sa[k];
+            b1 = sb[k];
+            nw = 2;
         } else {
-            win[3] = b[s];   // a third range: widen the second one over the gap
+            b1 = sb[k];   // a third range: widen the second one over the gap
         }
     }
+    win[0] = a0;
+    win[1] = b0;
+    win[2] = a1;
+    win[3] = b1;
 }
 
 // ---------------------------------------------------------------- per-lane piece
@@ -235,39 +303,40 @@ struct LaneP {
 
 // The index range is kept inside the grid whatever the description holds, so that no
 // column can leave x.
-template <typename R, int DIM>
-__device__ __forceinline__ void lane_ray(const JobDev &J, const RayP<R> &r, LaneP<R> &p) {
+template <typename R, int DIM, int WHICH>
+__device__ __forceinline__ void lane_ray(const JobDev &J, RowRefD<R, DIM> w, LaneP<R> &p) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        p.c0[d] = r.c0[d];
-        p.c1[d] = r.c1[d];
+        p.c0[d] = RV(w, ray[WHICH].c0[d]);
+        p.c1[d] = RV(w, ray[WHICH].c1[d]);
         p.c2[d] = R(0);
         p.c3[d] = R(0);
-        p.fS[d] = r.fS[d];
-        p.fE[d] = r.fE[d];
+        p.fS[d] = RV(w, ray[WHICH].fS[d]);
+        p.fE[d] = RV(w, ray[WHICH].fE[d]);
         const int top = J.n[d] - 1;
-        const int lo = r.lo[d] < 0 ? 0 : (r.lo[d] > top ? top : r.lo[d]);
-        const int hi = r.hi[d] < lo ? lo : (r.hi[d] > top ? top : r.hi[d]);
+        const int rlo = RV(w, ray[WHICH].lo[d]), rhi = RV(w, ray[WHICH].hi[d]);
+        const int lo = rlo < 0 ? 0 : (rlo > top ? top : rlo);
+        const int hi = rhi < lo ? lo : (rhi > top ? top : rhi);
         p.lo[d] = R(lo);
         p.hi[d] = R(hi);
     }
-    p.M = r.M;
+    p.M = RV(w, ray[WHICH].M);
 }
 
 template <typename R, int DIM>
-__device__ __forceinline__ void lane_spline(const JobDev &J, const SplP<R> &s, LaneP<R> &p) {
+__device__ __forceinline__ void lane_spline(const JobDev &J, RowRefD<R, DIM> w, LaneP<R> &p) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        p.c0[d] = s.c0[d];
-        p.c1[d] = s.c1[d];
-        p.c2[d] = s.c2[d];
-        p.c3[d] = s.c3[d];
-        p.fS[d] = s.fS[d];
-        p.fE[d] = s.fE[d];
+        p.c0[d] = RV(w, spl.c0[d]);
+        p.c1[d] = RV(w, spl.c1[d]);
+        p.c2[d] = RV(w, spl.c2[d]);
+        p.c3[d] = RV(w, spl.c3[d]);
+        p.fS[d] = RV(w, spl.fS[d]);
+        p.fE[d] = RV(w, spl.fE[d]);
         p.lo[d] = R(0);
         p.hi[d] = R(J.n[d] - 1);
     }
-    p.M = s.N;
+    p.M = RV(w, spl.N);
 }
 
 // End of item m - 1 (m = 0: the piece's start point).  mf == m.
@@ -601,14 +670,14 @@ __device__ __forceinline__ int32_t col_at(const int32_t stride[3], const int I[3
 // Walk one row with the whole wave; n_entries = entries produced.
 // FAST: every item crosses each axis at most once (the row's `fast` flag).
 template <typename R, int DIM, typename TW, bool FAST>
-__device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int kind, RowOut<TW> &out, int lane,
+__device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int kind, RowOut<TW> &out, int lane,
                                          int64_t &n_entries) {
     // item counts as the count pass writes them; the bounds only matter for a
     // description it did not write (the walk then stays finite and the count check fails)
     const int mmax = J.nmax + 1;
-    const int M0 = min(max(w.ray[0].M, 0), mmax);
-    const int Ns = (kind == 2) ? min(max(w.spl.N, 0), (1 << 22) + 1) : 0;
-    const int M1 = (kind == 2) ? min(max(w.ray[1].M, 0), mmax) : 0;
+    const int M0 = min(max(RV(w, ray[0].M), 0), mmax);
+    const int Ns = (kind == 2) ? min(max(RV(w, spl.N), 0), (1 << 22) + 1) : 0;
+    const int M1 = (kind == 2) ? min(max(RV(w, ray[1].M), 0), mmax) : 0;
     const int T = M0 + Ns + M1;
     n_entries = 0;
     if (T == 0) return;
@@ -626,13 +695,13 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
     int base = 0;
     const bool spl = lane >= L0 && lane < L0 + Ls;
     if (lane < L0) {
-        lane_ray<R, DIM>(J, w.ray[0], P);
+        lane_ray<R, DIM, 0>(J, w, P);
         base = lane * K;
     } else if (spl) {
-        lane_spline<R, DIM>(J, w.spl, P);
+        lane_spline<R, DIM>(J, w, P);
         base = (lane - L0) * K;
     } else {
-        lane_ray<R, DIM>(J, w.ray[1], P);
+        lane_ray<R, DIM, 1>(J, w, P);
         base = (lane - L0 - Ls) * K;
     }
     P.M = (lane < L0) ? M0 : (spl ? Ns : (lane <= last_lane ? M1 : 0));
@@ -652,8 +721,8 @@ __device__ __forceinline__ void wave_row(const JobDev &J, const RowV<R> &w, int 
         if (spl) {
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-                mono = mono && !(first < w.spl.win[d][1] && last > w.spl.win[d][0]);
-                mono = mono && !(first < w.spl.win[d][3] && last > w.spl.win[d][2]);
+                mono = mono && !(first < RV(w, spl.win[d][1]) && last > RV(w, spl.win[d][0]));
+                mono = mono && !(first < RV(w, spl.win[d][3]) && last > RV(w, spl.win[d][2]));
             }
         }
         if (mono) {
@@ -764,19 +833,19 @@ __device__ __forceinline__ R spline_max_rate(R c1, R c2, R c3, int N) {
 }
 
 template <typename R, int DIM>
-__device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowV<R> &w) {
+__device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowRefD<R, DIM> w) {
     PathGeom<R> p;
     if (J.path == 1) make_path<R, DIM, true>(J, g, p);
     else make_path<R, DIM, false>(J, g, p);
     const R ninf = -r_inf<R>(), pinf = r_inf<R>();
-    w.spl.N = 0;
-    w.ray[1].M = 0;
-    w.fast = 1;   // every item crosses each axis at most once
+    int kind = 0, fast = 1;   // fast: every item crosses each axis at most once
+    RV(w, spl.N) = 0;
+    RV(w, ray[1].M) = 0;
     if (!p.curved) {
         R lo = ninf, hi = pinf;
         const bool hit = clip_box<R, DIM>(J, p.Q, p.u, lo, hi);
-        w.kind = hit ? 1 : 0;
-        if (!make_ray<R, DIM>(J, p.Q, p.u, lo, hi, hit, w.ray[0])) w.fast = 0;
+        kind = hit ? 1 : 0;
+        if (!make_ray<R, DIM, 0>(J, p.Q, p.u, lo, hi, hit, w)) fast = 0;
     } else {
         // the spline lies in the convex hull of its Bezier control points
         R b1[3], b2[3];
@@ -787,52 +856,58 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowV<R> &w
         }
         const bool in = hull_inside<R, DIM>(J, p.P0) && hull_inside<R, DIM>(J, p.P1) &&
                         hull_inside<R, DIM>(J, b1) && hull_inside<R, DIM>(J, b2);
-        w.kind = in ? 2 : 3;
-        w.ray[0].M = 0;
+        kind = in ? 2 : 3;
+        RV(w, ray[0].M) = 0;
         if (in) {
             R lo = ninf, hi = R(0);
             bool hit = clip_box<R, DIM>(J, p.P0, p.d0, lo, hi);
-            if (!make_ray<R, DIM>(J, p.P0, p.d0, lo, hi, hit, w.ray[0])) w.fast = 0;
+            if (!make_ray<R, DIM, 0>(J, p.P0, p.d0, lo, hi, hit, w)) fast = 0;
             lo = R(0);
             hi = pinf;
             hit = clip_box<R, DIM>(J, p.P1, p.d1, lo, hi);
-            if (!make_ray<R, DIM>(J, p.P1, p.d1, lo, hi, hit, w.ray[1])) w.fast = 0;
+            if (!make_ray<R, DIM, 1>(J, p.P1, p.d1, lo, hi, hit, w)) fast = 0;
             const R iN = p.invN, iN2 = iN * iN, iN3 = iN2 * iN;
             const R thr = sizeof(R) == 8 ? R(1e-9) : R(1e-2);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const R ih = (d < DIM) ? R(J.invh[d]) : R(0);
-                w.spl.fS[d] = (d < DIM) ? (p.P0[d] - R(J.o[d])) * ih : R(0);
-                w.spl.fE[d] = (d < DIM) ? (p.P1[d] - R(J.o[d])) * ih : R(0);
-                w.spl.c0[d] = w.spl.fS[d];
-                w.spl.c1[d] = p.c1[d] * ih * iN;
-                w.spl.c2[d] = p.c2[d] * ih * iN2;
-                w.spl.c3[d] = p.c3[d] * ih * iN3;
+                const R fS = (d < DIM) ? (p.P0[d] - R(J.o[d])) * ih : R(0);
+                const R c1 = p.c1[d] * ih * iN, c2 = p.c2[d] * ih * iN2, c3 = p.c3[d] * ih * iN3;
+                RV(w, spl.fS[d]) = fS;
+                RV(w, spl.fE[d]) = (d < DIM) ? (p.P1[d] - R(J.o[d])) * ih : R(0);
+                RV(w, spl.c0[d]) = fS;
+                RV(w, spl.c1[d]) = c1;
+                RV(w, spl.c2[d]) = c2;
+                RV(w, spl.c3[d]) = c3;
+                int32_t win[4] = {-1, -1, -1, -1};
                 if (d < DIM) {
-                    spline_windows<R>(w.spl.c1[d], w.spl.c2[d], w.spl.c3[d], p.N, thr, w.spl.win[d]);
+                    spline_windows<R>(c1, c2, c3, p.N, thr, win);
                     // a chord moves less than one voxel along d when |F'| < 1 over [0, N]
-                    if (!(spline_max_rate<R>(w.spl.c1[d], w.spl.c2[d], w.spl.c3[d], p.N) < R(0.999))) w.fast = 0;
-                } else {
-                    w.spl.win[d][0] = w.spl.win[d][1] = w.spl.win[d][2] = w.spl.win[d][3] = -1;
+                    if (!(spline_max_rate<R>(c1, c2, c3, p.N) < R(0.999))) fast = 0;
                 }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) RV(w, spl.win[d][k]) = win[k];
             }
-            w.spl.N = p.N;
+            RV(w, spl.N) = p.N;
         }
     }
-    w.bfac = 1.0;
+    RV(w, kind) = kind;
+    RV(w, fast) = fast;
+    double bfac = 1.0;
     if (J.noise > 0.0) {
         R z1, z2;
         normal_pair<R>(J.seed, 4, (uint64_t)g, z1, z2);
-        w.bfac = (double)(R(1) + R(J.noise) * z1);
+        bfac = (double)(R(1) + R(J.noise) * z1);
     }
+    RV(w, bfac) = bfac;
 }
 
 // Crossings of the spline, axis by axis: index differences over the monotone stretches,
 // sample by sample inside the recorded ranges.
 template <typename R, int DIM>
-__device__ __forceinline__ int64_t spline_crossings(const JobDev &J, const SplP<R> &s) {
+__device__ __forceinline__ int64_t spline_crossings(const JobDev &J, RowRefD<R, DIM> w) {
     LaneP<R> p;
-    lane_spline<R, DIM>(J, s, p);
+    lane_spline<R, DIM>(J, w, p);
     int64_t c = 0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -845,7 +920,7 @@ __device__ __forceinline__ int64_t spline_crossings(const JobDev &J, const SplP<
         };
         int Iprev = idx(0);
         for (int k = 0; k < 2; ++k) {
-            const int a = s.win[d][2 * k], b = s.win[d][2 * k + 1];
+            const int a = RV(w, spl.win[d][2 * k]), b = RV(w, spl.win[d][2 * k + 1]);
             if (a < 0) continue;
             int Ia = idx(a);
             c += abs(Ia - Iprev);
@@ -856,7 +931,7 @@ __device__ __forceinline__ int64_t spline_crossings(const JobDev &J, const SplP<
             }
             Iprev = Ia;
         }
-        c += abs(idx(s.N) - Iprev);
+        c += abs(idx(p.M) - Iprev);
     }
     return c;
 }
@@ -865,32 +940,33 @@ __device__ __forceinline__ int64_t spline_crossings(const JobDev &J, const SplP<
 // its items, exactly as wave_row produces them; the per-lane walk for kind 3.  A row
 // with more entries than a wave stages becomes kind 3 here.
 template <typename R, int DIM>
-__device__ __forceinline__ int64_t count_row(const JobDev &J, RowV<R> &w, int64_t g) {
-    if (w.kind == 0) return 0;
-    if (w.kind == 3) {
+__device__ __forceinline__ int64_t count_row(const JobDev &J, RowRefD<R, DIM> w, int64_t g) {
+    const int kind = RV(w, kind);
+    if (kind == 0) return 0;
+    if (kind == 3) {
         CountSink s;
         trace_row<R, DIM, true>(J, g, s);
         return s.n;
     }
     int64_t c = 0;
     bool any = false;
-    if (w.ray[0].M > 0) {
+    if (RV(w, ray[0].M) > 0) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) c += w.ray[0].hi[d] - w.ray[0].lo[d];
+        for (int d = 0; d < DIM; ++d) c += RV(w, ray[0].hi[d]) - RV(w, ray[0].lo[d]);
         any = true;
     }
-    if (w.kind == 2) {
-        c += spline_crossings<R, DIM>(J, w.spl);
+    if (kind == 2) {
+        c += spline_crossings<R, DIM>(J, w);
         any = true;
-        if (w.ray[1].M > 0) {
+        if (RV(w, ray[1].M) > 0) {
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) c += w.ray[1].hi[d] - w.ray[1].lo[d];
+            for (int d = 0; d < DIM; ++d) c += RV(w, ray[1].hi[d]) - RV(w, ray[1].lo[d]);
         }
     }
     const int64_t n = any ? c + 1 : 0;
     if (n > STAGE_CAP) {
         // more entries than the wave's LDS slice holds: the per-lane walk takes the row
-        w.kind = 3;
+        RV(w, kind) = 3;
         CountSink s;
         trace_row<R, DIM, true>(J, g, s);
         return s.n;
@@ -900,19 +976,22 @@ __device__ __forceinline__ int64_t count_row(const JobDev &J, RowV<R> &w, int64_
 
 // Emit pass over rows [r0, r0 + nr) of job J by one wavefront.
 template <typename R, int DIM, bool STORE>
-__device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *__restrict__ rows, int64_t r0,
-                                               int nr, int lane, uint2 *stage, int32_t *status) {
+__device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, int64_t r0, int nr, int lane,
+                                               uint2 *stage, int32_t *status) {
     using TW = typename std::conditional<std::is_same<R, double>::value, double, float>::type;
     const int64_t rend = (r0 + nr < J.row_count) ? r0 + nr : J.row_count;
     bool bad = false;
     for (int64_t r = r0; r < rend; ++r) {
-        const RowV<R> &w = rows[r];
-        // start fetching the description of the row after next (8 B per lane): it is in
-        // cache when the lanes load their pieces of it
-        uint2 next = make_uint2(0u, 0u);
-        constexpr int NW = (int)((sizeof(RowV<R>) + 7) / 8);
-        if (r + 2 < rend && lane < NW) next = reinterpret_cast<const uint2 *>(rows + r + 2)[lane];
-        const int kind = w.kind;
+        const RowRefD<R, DIM> w = row_ref<R, DIM>(rowbuf, J, r);
+        // start fetching the next row's description (one 16-byte chunk per lane): it is
+        // in cache when the lanes load their pieces of it
+        uint4 next = make_uint4(0u, 0u, 0u, 0u);
+        constexpr int NC = (int)(rv_bytes<R>() / 16);
+        if (r + 1 < rend && lane < NC) {
+            const RowRefD<R, DIM> wn = row_ref<R, DIM>(rowbuf, J, r + 1);
+            next = wn.template at<uint4>((size_t)lane * 16);
+        }
+        const int kind = RV(w, kind);
         if (kind == 3) continue;   // walked by the per-lane kernel
         if (kind < 0 || kind > 3) {   // not a description of the count pass
             if (lane == 0) set_status_dev(status, PCT_EINTERNAL);
@@ -946,23 +1025,23 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, const RowV<R> *_
         out.vf = gptr((float *)J.vals + pos);
         int64_t ne = 0;
         if (kind != 0) {
-            if (w.fast) wave_row<R, DIM, TW, true>(J, w, kind, out, lane, ne);
+            if (RV(w, fast)) wave_row<R, DIM, TW, true>(J, w, kind, out, lane, ne);
             else wave_row<R, DIM, TW, false>(J, w, kind, out, lane, ne);
         }
         bad |= out.bad;
         if (out.store && ne != out.len && lane == 0) set_status_dev(status, PCT_EINTERNAL);
         if (out.want_b) {
             const TW bs = (TW)wave_sum((double)out.wacc);
-            if (lane == 0) J.b[r] = (float)(bs * (TW)w.bfac);
+            if (lane == 0) J.b[r] = (float)(bs * (TW)RV(w, bfac));
         }
-        asm volatile("" ::"v"(next.x), "v"(next.y));   // keeps the fetch; waits for it only here
+        asm volatile("" ::"v"(next.x), "v"(next.y), "v"(next.z), "v"(next.w));   // keeps the fetch; waits here
     }
     if (__builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) set_status_dev(status, PCT_EINTERNAL);
 }
 
 // Rows whose spline may leave the box (kind 3): one lane per row, general walk.
 template <typename R, int DIM, bool STORE>
-__device__ __forceinline__ void emit_row_lane(const JobDev &J, const RowV<R> &w, int64_t r, int32_t *status) {
+__device__ __forceinline__ void emit_row_lane(const JobDev &J, RowRefD<R, DIM> w, int64_t r, int32_t *status) {
     using TW = typename std::conditional<std::is_same<R, double>::value, double, float>::type;
     EmitSink<R, TW> s;
     s.cols = J.cols;
@@ -984,7 +1063,7 @@ __device__ __forceinline__ void emit_row_lane(const JobDev &J, const RowV<R> &w,
     trace_row<R, DIM, true>(J, J.row_begin + r, s);
     s.flush();
     if (s.store && s.pos != s.end) set_status_dev(status, PCT_EINTERNAL);
-    if (s.want_b) J.b[r] = (float)(s.wepl * (TW)w.bfac);
+    if (s.want_b) J.b[r] = (float)(s.wepl * (TW)RV(w, bfac));
 }
 
 }  // namespace pct
