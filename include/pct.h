@@ -56,6 +56,9 @@ typedef int32_t pct_status;
 #define PCT_MIXED      0   /* FP64 geometry and traversal order, FP32 lengths, FP64 WEPL sum */
 #define PCT_PLAIN_F32  1   /* FP32 everywhere (comparison form)                              */
 
+#define PCT_SCATTER_FIXED    0  /* exit pair widths and correlation as given in the beam     */
+#define PCT_SCATTER_HIGHLAND 1  /* per proton from Highland's formula (Sec. II-B), see below */
+
 #define PCT_MAX_REGIONS 16
 
 /* One region of a non-homogeneous ellipse object (Sec. II-A).  A point belongs to the
@@ -107,6 +110,18 @@ typedef struct {
                                     2^22 samples per outer-boundary diameter x 6, else
                                     PCT_ERANGE */
     double noise_rel;            /* relative WEPL noise sigma, >= 0 (0: noiseless) */
+    /* Multiple-scattering model of the exit pair (Hermite paths; Sec. II-B).
+     * PCT_SCATTER_FIXED: sigma_out_rad, sigma_lat_mm and rho as given above.
+     * PCT_SCATTER_HIGHLAND: with x the length of the straight entry line inside the outer
+     * boundary (mm), Highland's width with the Particle Data Group constants
+     *   theta0 = 13.6 MeV / (beta c p) * sqrt(x / X0) * (1 + 0.038 ln(x / (X0 beta^2)))
+     * (taken as 0 where the bracket is negative), for a proton of the constant kinetic
+     * energy energy_mev, and the exit pair of a uniform slab of thickness x:
+     *   sigma_out = theta0, sigma_lat = theta0 x / sqrt(3), rho = sqrt(3) / 2;
+     * sigma_out_rad, sigma_lat_mm and rho are then ignored (but must still be valid). */
+    int32_t scatter;             /* PCT_SCATTER_FIXED | PCT_SCATTER_HIGHLAND */
+    double energy_mev;           /* Highland: kinetic energy, 1..10000 MeV */
+    double x0_mm;                /* Highland: radiation length of the medium, > 0 (water 360.8) */
 } pct_beam;
 
 /* One simulation job: one phantom, one beam, one range of rows. */
@@ -121,6 +136,10 @@ typedef struct {
     float *b_dev;                /* row_count entries; may be NULL in pct_emit_csr */
     int32_t val_dtype;           /* PCT_F32 | PCT_F16 */
     int32_t precision;           /* PCT_MIXED | PCT_PLAIN_F32; equal for all jobs of a call */
+    double chord_mm;             /* 0: every stored value is the path length in its voxel;
+                                    > 0: every stored value is chord_mm, the constant chord
+                                    length of the paper's examples (Sec. II-C), while b stays
+                                    the WEPL of the true path lengths */
 } pct_job;
 
 /* Human-readable name of a status code (static string). */

@@ -49,13 +49,16 @@ class Beam(C.Structure):
                 ("dangle_deg", C.c_double), ("n_protons", C.c_int64),
                 ("t_range", C.c_double * 2), ("v_range", C.c_double * 2), ("path", C.c_int32),
                 ("sigma_in", C.c_double), ("sigma_out", C.c_double), ("sigma_lat", C.c_double),
-                ("rho", C.c_double), ("step", C.c_double), ("noise_rel", C.c_double)]
+                ("rho", C.c_double), ("step", C.c_double), ("noise_rel", C.c_double),
+                ("scatter", C.c_int32), ("energy_mev", C.c_double), ("x0_mm", C.c_double)]
 
 
 class Path(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_samples", C.c_int32), ("t", C.c_double),
                 ("v", C.c_double), ("P0", C.c_double * 3), ("P1", C.c_double * 3),
-                ("d0", C.c_double * 3), ("d1", C.c_double * 3), ("L", C.c_double)]
+                ("d0", C.c_double * 3), ("d1", C.c_double * 3), ("L", C.c_double),
+                ("thickness", C.c_double), ("sigma_out", C.c_double), ("sigma_lat", C.c_double),
+                ("rho", C.c_double)]
 
 
 _lib = None
@@ -82,6 +85,8 @@ def lib():
                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.or_boundary_hit.restype = C.c_int
         L.or_hermite.argtypes = [C.POINTER(C.c_double)] * 4 + [C.c_double, C.c_double, C.POINTER(C.c_double)]
+        L.or_highland.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.or_highland.restype = C.c_double
         L.or_rsp_at.argtypes = [C.POINTER(Phantom), C.POINTER(C.c_double)]
         L.or_rsp_at.restype = C.c_double
         L.or_phantom_build.argtypes = [C.POINTER(Phantom), C.c_void_p]
@@ -151,6 +156,9 @@ def make_beam(bm: dict) -> Beam:
     b.rho = float(bm.get("rho", 0.0))
     b.step = float(bm.get("step", 0.25))
     b.noise_rel = float(bm.get("noise_rel", 0.0))
+    b.scatter = {"fixed": 0, "highland": 1}[bm.get("scatter", "fixed")]
+    b.energy_mev = float(bm.get("energy_mev", 200.0))
+    b.x0_mm = float(bm.get("x0_mm", 360.8))
     return b
 
 
@@ -210,6 +218,11 @@ def hermite(P0, d0, P1, d1, L, s):
     return list(out)
 
 
+def highland(energy_mev, x0_mm, x_mm):
+    """Highland's projected multiple-scattering width (rad) for a proton."""
+    return lib().or_highland(float(energy_mev), float(x0_mm), float(x_mm))
+
+
 def rsp_at(ph: dict, p):
     pp, keep = make_phantom(ph)
     q = (C.c_double * 3)(*(list(p) + [0.0] * (3 - len(p))))
@@ -264,6 +277,12 @@ def run(cfg: dict, rows=None, x: np.ndarray | None = None, with_paths: bool = Fa
     x = np.ascontiguousarray(x, dtype=np.float32)
     res = lib().or_run(C.byref(p), C.byref(b), _ptr(x), _ptr(rows), len(rows))
     out = _collect(res, len(rows), with_paths)
+    chord = cfg.get("chord_mm") or 0.0
+    if chord > 0.0:
+        # constant chord length: every entry of A holds the constant; b keeps the WEPL
+        # of the true lengths (Sec. II-C, Sec. III)
+        out["true_vals"] = out["vals"]
+        out["vals"] = np.full_like(out["vals"], float(chord))
     out["x"] = x
     out["rows"] = rows
     return out

@@ -22,7 +22,8 @@
  *     giving one CSR row of A whose entries are the chord lengths of the path in each
  *     voxel [Sec. II-C];
  *   - the WEPL b_i as the inner product of row i with x, optionally with noise
- *     [Sec. II-C].
+ *     [Sec. II-C];
+ *   - optionally, exit-pair widths per proton from Highland's formula [Sec. II-B].
  * Where the paper is silent the readings are those listed in the design notes of the
  * repository (Gaussian relative WEPL noise instead of the PSTAR/Tschalar model, a
  * counter-based Philox4x32-10 generator instead of C rand(), a cubic Hermite curve for
@@ -78,6 +79,9 @@ typedef struct {
     int32_t path;
     double sigma_in, sigma_out, sigma_lat, rho, step;
     double noise_rel;
+    int32_t scatter;        /* 0: widths as given; 1: Highland per proton */
+    double energy_mev;      /* Highland: constant kinetic energy */
+    double x0_mm;           /* Highland: radiation length of the medium */
 } or_beam;
 
 /* ------------------------------------------------------------ Philox4x32-10 (RNG) */
@@ -426,7 +430,27 @@ typedef struct {
     double t, v;
     double P0[3], P1[3], d0[3], d1[3];
     double L;
+    double thickness;      /* straight entry line inside the outer boundary (mm) */
+    double sigma_out, sigma_lat, rho;   /* exit-pair widths and correlation used */
 } or_path;
+
+/* Highland's projected width of the multiple-scattering angle with the Particle Data
+ * Group constants [Sec. II-B]: for a particle of unit charge, momentum p and speed
+ * beta c after a thickness x of a medium of radiation length X0,
+ *     theta0 = 13.6 MeV / (beta c p) sqrt(x / X0) (1 + 0.038 ln(x / (X0 beta^2))).
+ * The proton keeps the kinetic energy T over the whole path: with the rest energy m,
+ * p c = sqrt(T^2 + 2 T m) and beta = p c / (T + m).  Where the bracket would be
+ * negative (thicknesses far below the formula's range) the width is 0. */
+double or_highland(double T_mev, double x0_mm, double x_mm)
+{
+    const double m = 938.27208816;      /* proton rest energy, MeV */
+    const double pc = sqrt(T_mev * T_mev + 2.0 * T_mev * m);
+    const double beta = pc / (T_mev + m);
+    if (!(x_mm > 0.0)) return 0.0;
+    const double bracket = 1.0 + 0.038 * log(x_mm / (x0_mm * beta * beta));
+    if (bracket < 0.0) return 0.0;
+    return 13.6 / (beta * pc) * sqrt(x_mm / x0_mm) * bracket;
+}
 
 static void tangency(or_row *row, double half_chord)
 {
@@ -484,17 +508,31 @@ static void trace_proton(or_row *row, const or_beam *bm, int64_t g, or_path *pat
     double P0[3], P1s[3];
     for (int i = 0; i < 3; ++i) { P0[i] = Q[i] + l1 * d0[i]; P1s[i] = Q[i] + l2 * d0[i]; }
 
-    /* exit pair per plane: lateral displacement and exit angle, correlation rho */
-    const double cr = sqrt(1.0 - bm->rho * bm->rho);
+    /* exit pair per plane: lateral displacement and exit angle, correlation rho; with
+     * Highland's model the widths follow from the thickness x of the phantom along the
+     * entry line, as for a uniform slab: sigma_out = theta0, sigma_lat = theta0 x / sqrt 3,
+     * correlation sqrt(3) / 2 */
+    double sig_out = bm->sigma_out, sig_lat = bm->sigma_lat, rho = bm->rho;
+    path->thickness = l2 - l1;
+    if (bm->scatter == 1) {
+        const double x = l2 - l1;
+        sig_out = or_highland(bm->energy_mev, bm->x0_mm, x);
+        sig_lat = sig_out * x / sqrt(3.0);
+        rho = sqrt(3.0) / 2.0;
+    }
+    path->sigma_out = sig_out;
+    path->sigma_lat = sig_lat;
+    path->rho = rho;
+    const double cr = sqrt(1.0 - rho * rho);
     double z1, z2;
     or_normal_pair(bm->seed, 2, (uint64_t)g, &z1, &z2);
-    const double lat_t = bm->sigma_lat * z1;
-    const double ang_t = bm->sigma_out * (bm->rho * z1 + cr * z2);
+    const double lat_t = sig_lat * z1;
+    const double ang_t = sig_out * (rho * z1 + cr * z2);
     double lat_v = 0.0, ang_v = 0.0;
     if (dim == 3) {
         or_normal_pair(bm->seed, 3, (uint64_t)g, &z1, &z2);
-        lat_v = bm->sigma_lat * z1;
-        ang_v = bm->sigma_out * (bm->rho * z1 + cr * z2);
+        lat_v = sig_lat * z1;
+        ang_v = sig_out * (rho * z1 + cr * z2);
     }
     double nt[3], nv[3];
     const double tdot = dot3(t_hat, d0), vdot = dot3(v_hat, d0);

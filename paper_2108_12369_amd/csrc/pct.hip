@@ -370,6 +370,11 @@ static pct_status check_beam(const pct_beam *b) {
     if (b->rho < -1.0 || b->rho > 1.0) return PCT_EINVAL;
     if (b->sigma_in_rad > 0.1 || b->sigma_out_rad > 0.1) return PCT_EINVAL;
     if (b->path == PCT_HERMITE && !(b->step_mm > 0.0)) return PCT_EINVAL;
+    if (b->scatter != PCT_SCATTER_FIXED && b->scatter != PCT_SCATTER_HIGHLAND) return PCT_EINVAL;
+    if (b->scatter == PCT_SCATTER_HIGHLAND) {
+        if (!(b->energy_mev >= 1.0 && b->energy_mev <= 10000.0)) return PCT_EINVAL;
+        if (!(b->x0_mm > 0.0) || !finite_d(b->x0_mm)) return PCT_EINVAL;
+    }
     // (g + 1) * K must not overflow int64 in the row decode
     if (b->n_protons > 0 && (double)b->n_protons * (double)b->n_angles > 9.0e18) return PCT_ERANGE;
     return PCT_OK;
@@ -387,6 +392,7 @@ static pct_status check_jobs(int32_t n_jobs, const pct_job *jobs, bool need_csr,
         if (jb.precision != PCT_MIXED && jb.precision != PCT_PLAIN_F32) return PCT_EINVAL;
         if (jb.precision != jobs[0].precision) return PCT_EINVAL;
         if (jb.nnz_capacity < 0) return PCT_EINVAL;
+        if (!(jb.chord_mm >= 0.0) || !(jb.chord_mm < 1.0e30)) return PCT_EINVAL;
         if (!jb.x_dev && (need_b || jb.b_dev)) return PCT_EINVAL;
         if (need_csr && !jb.row_ptr_dev) return PCT_EINVAL;
         if (need_csr && jb.nnz_capacity > 0 && (!jb.cols_dev || !jb.vals_dev)) return PCT_EINVAL;
@@ -443,6 +449,17 @@ static JobDev make_job(const pct_job &jb, int64_t count_off, int64_t tile_base) 
     J.crho = sqrt(1.0 - bm.rho * bm.rho);
     J.step = bm.step_mm;
     J.noise = bm.noise_rel;
+    J.highland = bm.scatter == PCT_SCATTER_HIGHLAND ? 1 : 0;
+    if (J.highland) {
+        // proton of kinetic energy T: p c = sqrt(T (T + 2 m)), beta = p c / (T + m)
+        const double mp = 938.27208816;   // proton mass, MeV
+        const double T = bm.energy_mev, E = T + mp, pc = sqrt(T * (T + 2.0 * mp));
+        const double beta = pc / E;
+        J.hl_k = 13.6 / (beta * pc);
+        J.hl_x0inv = 1.0 / bm.x0_mm;
+        J.hl_lnb2 = log(beta * beta);
+    }
+    J.chord = (float)jb.chord_mm;
     J.x = jb.x_dev;
     J.row_ptr = jb.row_ptr_dev;
     J.cols = jb.cols_dev;

@@ -54,6 +54,11 @@ struct JobDev {
     int64_t n_etiles;    // launch order of the jobs, 4 * rpw rows each)
     int32_t rpw;         // rows per wavefront in the emit pass
     int32_t nmax;        // largest n[d]
+    int32_t highland;    // exit pair widths per proton from Highland's formula
+    float chord;         // > 0: the stored value of every entry (constant chord length)
+    double hl_k;         // Highland: 13.6 MeV / (beta c p)
+    double hl_x0inv;     // Highland: 1 / X0 (1/mm)
+    double hl_lnb2;      // Highland: ln(beta^2)
 };
 
 // ------------------------------------------------------------------ math helpers
@@ -227,15 +232,17 @@ struct EmitSink {
     float plen = 0.0f;
     float px = 0.0f;
     TW wepl = TW(0);
+    float chord = 0.0f;   // > 0: stored instead of the length (b keeps the length)
     bool store, half, want_b;
 
     __device__ __forceinline__ void flush() {
         if (pcol >= 0) {
             if (want_b) wepl += (TW)plen * (TW)px;
             if (store && pos < end) {
+                const float sv = chord > 0.0f ? chord : plen;
                 cols[pos] = pcol;
-                if (half) ((__half *)vals)[pos] = __float2half_rn(plen);
-                else ((float *)vals)[pos] = plen;
+                if (half) ((__half *)vals)[pos] = __float2half_rn(sv);
+                else ((float *)vals)[pos] = sv;
             }
             ++pos;
         }
@@ -526,14 +533,29 @@ __device__ __forceinline__ void make_path(const JobDev &J, int64_t g, PathGeom<R
         }
         R z1, z2;
         normal_pair<R>(J.seed, 2, (uint64_t)g, z1, z2);
-        const R crho = R(J.crho), rho = R(J.rho);
-        const R lat_t = R(J.sig_lat) * z1;
-        const R ang_t = R(J.sig_out) * (rho * z1 + crho * z2);
+        R crho = R(J.crho), rho = R(J.rho), sig_lat = R(J.sig_lat), sig_out = R(J.sig_out);
+        if (J.highland) {
+            // Highland's width for the straight entry line's length inside the outer
+            // boundary, and the exit pair of a uniform slab of that thickness [Sec. II-B]
+            const R x = l2 - l1;
+            const R u = x * R(J.hl_x0inv);
+            R th0 = R(0);
+            if (u > R(0)) {
+                const R br = R(1) + R(0.038) * (r_log<R>(u) - R(J.hl_lnb2));
+                th0 = br > R(0) ? R(J.hl_k) * r_sqrt<R>(u) * br : R(0);
+            }
+            sig_out = th0;
+            sig_lat = th0 * x * R(0.57735026918962576451);   // 1/sqrt(3)
+            rho = R(0.86602540378443864676);                  // sqrt(3)/2
+            crho = R(0.5);
+        }
+        const R lat_t = sig_lat * z1;
+        const R ang_t = sig_out * (rho * z1 + crho * z2);
         R lat_v = R(0), ang_v = R(0);
         if (DIM == 3) {
             normal_pair<R>(J.seed, 3, (uint64_t)g, z1, z2);
-            lat_v = R(J.sig_lat) * z1;
-            ang_v = R(J.sig_out) * (rho * z1 + crho * z2);
+            lat_v = sig_lat * z1;
+            ang_v = sig_out * (rho * z1 + crho * z2);
         }
         const R tdot = th[0] * d0[0] + th[1] * d0[1];
         R nt[3] = {th[0] - tdot * d0[0], th[1] - tdot * d0[1], -tdot * d0[2]};

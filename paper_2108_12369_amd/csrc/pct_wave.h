@@ -501,6 +501,7 @@ struct RowOut {
     uint2 *stage;   // the wave's LDS slice
     uint32_t nvox;  // size of x: every gather index is kept below it
     int32_t len;
+    float chord;    // > 0: stored instead of the length (b keeps the length)
     float wepl;
     TW wacc;
     bool store, half, want_b;
@@ -536,9 +537,10 @@ struct RowOut {
                     lv[u] = __uint_as_float(v.y);
                     if (want_b) xv[u] = x[v.x < nvox ? v.x : 0u];
                     if (store && e < m) {
+                        const float sv = chord > 0.f ? chord : lv[u];
                         cols[e] = (int32_t)v.x;
-                        if (half) vh[e] = __half_as_ushort(__float2half_rn(lv[u]));
-                        else vf[e] = lv[u];
+                        if (half) vh[e] = __half_as_ushort(__float2half_rn(sv));
+                        else vf[e] = sv;
                     }
                 }
             }
@@ -1008,6 +1010,7 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
         out.stage = stage;
         out.nvox = (uint32_t)J.n[0] * (uint32_t)J.n[1] * (uint32_t)(DIM == 3 ? J.n[2] : 1);
         out.len = 0;
+        out.chord = J.chord;
         int64_t pos = 0;
         if (STORE) {
             pos = J.row_ptr[r];
@@ -1050,6 +1053,7 @@ __device__ __forceinline__ void emit_row_lane(const JobDev &J, RowRefD<R, DIM> w
     s.half = (J.val_dtype == PCT_F16);
     s.want_b = (J.b != nullptr);
     s.store = STORE;
+    s.chord = J.chord;
     s.pos = 0;
     s.end = 0;
     if (STORE) {

@@ -22,12 +22,14 @@ PCT_F32, PCT_F16 = 0, 1
 PCT_MIXED, PCT_PLAIN_F32 = 0, 1
 PCT_MAX_REGIONS = 16
 PCT_ORDER_GIVEN, PCT_ORDER_LPT = 0, 1
+PCT_SCATTER_FIXED, PCT_SCATTER_HIGHLAND = 0, 1
 
 SHAPES = {"ellipse": PCT_ELLIPSE, "ellipsoid": PCT_ELLIPSOID}
 VOXELIZE = {"corner_avg": PCT_CORNER_AVG, "center": PCT_CENTER}
 PATHS = {"straight": PCT_STRAIGHT, "hermite": PCT_HERMITE}
 VAL_DTYPES = {"f32": PCT_F32, "f16": PCT_F16}
 PRECISIONS = {"mixed": PCT_MIXED, "plain_f32": PCT_PLAIN_F32}
+SCATTER = {"fixed": PCT_SCATTER_FIXED, "highland": PCT_SCATTER_HIGHLAND}
 
 SYMBOLS = ("pct_status_string", "pct_version", "pct_phantom_build", "pct_workspace_bytes",
            "pct_count_rows", "pct_emit_csr", "pct_wepl", "pct_device_status", "pct_set_launch_config",
@@ -57,14 +59,15 @@ class Beam(C.Structure):
                 ("row_begin", C.c_int64), ("row_count", C.c_int64), ("t_range", C.c_double * 2),
                 ("v_range", C.c_double * 2), ("sigma_in_rad", C.c_double),
                 ("sigma_out_rad", C.c_double), ("sigma_lat_mm", C.c_double), ("rho", C.c_double),
-                ("step_mm", C.c_double), ("noise_rel", C.c_double)]
+                ("step_mm", C.c_double), ("noise_rel", C.c_double), ("scatter", C.c_int32),
+                ("energy_mev", C.c_double), ("x0_mm", C.c_double)]
 
 
 class Job(C.Structure):
     _fields_ = [("phantom", C.POINTER(Phantom)), ("beam", C.POINTER(Beam)), ("x_dev", C.c_void_p),
                 ("row_ptr_dev", C.c_void_p), ("cols_dev", C.c_void_p), ("vals_dev", C.c_void_p),
                 ("nnz_capacity", C.c_int64), ("b_dev", C.c_void_p), ("val_dtype", C.c_int32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("chord_mm", C.c_double)]
 
 
 class LaunchConfig(C.Structure):
@@ -178,6 +181,9 @@ def make_beam(bm: dict, row_begin: int = 0, row_count: int | None = None) -> Bea
     b.rho = float(bm.get("rho", 0.0))
     b.step_mm = float(bm.get("step", 0.25))
     b.noise_rel = float(bm.get("noise_rel", 0.0))
+    b.scatter = SCATTER[bm.get("scatter", "fixed")]
+    b.energy_mev = float(bm.get("energy_mev", 200.0))
+    b.x0_mm = float(bm.get("x0_mm", 360.8))
     return b
 
 
@@ -205,7 +211,8 @@ class JobSet:
         self.entries = []
 
     def add(self, ph: dict, bm: dict, x, row_ptr=None, cols=None, vals=None, b=None,
-            nnz_capacity=0, val_dtype="f32", precision="mixed", row_begin=0, row_count=None):
+            nnz_capacity=0, val_dtype="f32", precision="mixed", row_begin=0, row_count=None,
+            chord_mm=0.0):
         p, arr = make_phantom(ph)
         be = make_beam(bm, row_begin, row_count)
         self._keep += [p, arr, be]
@@ -220,6 +227,7 @@ class JobSet:
         j.b_dev = _ptr(b)
         j.val_dtype = VAL_DTYPES[val_dtype]
         j.precision = PRECISIONS[precision]
+        j.chord_mm = float(chord_mm or 0.0)
         self.entries.append(j)
         return len(self.entries) - 1
 
@@ -321,6 +329,7 @@ def simulate(cfg: dict, row_begin: int = 0, row_count: int | None = None, precis
     Returns device tensors x, row_ptr (int64), cols (int32), vals (float32/float16), b."""
     ph, bm = cfg["phantom"], cfg["beam"]
     val_dtype = val_dtype or cfg.get("val_dtype", "f32")
+    chord = cfg.get("chord_mm") or 0.0
     if row_count is None:
         row_count = int(bm["n_protons"]) - row_begin
     if x is None:
@@ -338,7 +347,8 @@ def simulate(cfg: dict, row_begin: int = 0, row_count: int | None = None, precis
     b = torch.empty(max(row_count, 1), dtype=torch.float32, device=device)
     js2 = JobSet()
     js2.add(ph, bm, x, row_ptr=row_ptr, cols=cols, vals=vals, b=b, nnz_capacity=nnz,
-            val_dtype=val_dtype, precision=precision, row_begin=row_begin, row_count=row_count)
+            val_dtype=val_dtype, precision=precision, row_begin=row_begin, row_count=row_count,
+            chord_mm=chord)
     emit_csr(js2, ws, stream)
     st = device_status(ws, stream)
     _check(st, "device status after pct_emit_csr")

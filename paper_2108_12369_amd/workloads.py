@@ -69,18 +69,21 @@ def phantom(dim, n, h, regions, voxelize="corner_avg", origin=None):
 
 def beam(seed, n_angles, dangle_deg, n_protons, t_range, v_range=(0.0, 0.0), path="straight",
          sigma_in=0.0, sigma_out=0.0, sigma_lat=0.0, rho=0.0, step=0.25, noise_rel=0.0,
-         angle0_deg=0.0):
+         angle0_deg=0.0, scatter="fixed", energy_mev=200.0, x0_mm=360.8):
+    """scatter="highland": exit-pair widths per proton from Highland's formula for a
+    proton of kinetic energy energy_mev in a medium of radiation length x0_mm (water)."""
     return {"seed": int(seed), "n_angles": int(n_angles), "angle0_deg": float(angle0_deg),
             "dangle_deg": float(dangle_deg), "n_protons": int(n_protons),
             "t_range": [float(t_range[0]), float(t_range[1])],
             "v_range": [float(v_range[0]), float(v_range[1])], "path": path,
             "sigma_in": float(sigma_in), "sigma_out": float(sigma_out),
             "sigma_lat": float(sigma_lat), "rho": float(rho), "step": float(step),
-            "noise_rel": float(noise_rel)}
+            "noise_rel": float(noise_rel), "scatter": scatter, "energy_mev": float(energy_mev),
+            "x0_mm": float(x0_mm)}
 
 
-def workload(name, ph, bm, val_dtype="f32", chunk_rows=None):
-    return {"name": name, "phantom": ph, "beam": bm, "val_dtype": val_dtype,
+def workload(name, ph, bm, val_dtype="f32", chunk_rows=None, chord_mm=None):
+    return {"name": name, "phantom": ph, "beam": bm, "val_dtype": val_dtype, "chord_mm": chord_mm,
             "chunk_rows": chunk_rows}
 
 
@@ -131,6 +134,24 @@ def c_paper():
                     beam(12375, 180, 2.0, 640_000, (-125.0, 125.0)), "f32")
 
 
+def c_paper_const():
+    """The paper's example with its constant chord length: every entry of A is the
+    pixel size (1 mm) while b is the WEPL of the true path lengths."""
+    cfg = c_paper()
+    cfg["name"] = "paper-2d-neo1-200x160-straight-const-chord"
+    cfg["chord_mm"] = 1.0
+    return cfg
+
+
+def c1_highland():
+    """c1 with the exit-pair widths of every proton from Highland's formula (200 MeV in
+    water, X0 = 360.8 mm) instead of fixed widths."""
+    cfg = c1()
+    cfg["name"] = "c1h-2d-neo2-400sq-hermite-highland"
+    cfg["beam"].update(scatter="highland", energy_mev=200.0, x0_mm=360.8)
+    return cfg
+
+
 def c3_jobs(seed=12372, n_jobs=64):
     """64 uneven jobs drawn with numpy's PCG64: even ids 2D (N in 64..512 step 64), odd
     ids 3D (N in 64, 96, 128, 160), field of view 200 mm, outer semi-axes U[60,90],
@@ -170,7 +191,8 @@ def c3_jobs(seed=12372, n_jobs=64):
 
 
 def by_name(name: str):
-    table = {"c0": c0, "c1": c1, "c2": c2, "c4": c4, "paper": c_paper}
+    table = {"c0": c0, "c1": c1, "c2": c2, "c4": c4, "paper": c_paper,
+             "paper_const": c_paper_const, "c1_highland": c1_highland}
     return table[name]()
 
 

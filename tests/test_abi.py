@@ -55,8 +55,10 @@ int main(void) {
   F(pct_beam, n_angles) F(pct_beam, path) F(pct_beam, angle0_deg) F(pct_beam, n_protons)
   F(pct_beam, row_begin) F(pct_beam, row_count) F(pct_beam, t_range) F(pct_beam, v_range)
   F(pct_beam, sigma_in_rad) F(pct_beam, rho) F(pct_beam, step_mm) F(pct_beam, noise_rel)
+  F(pct_beam, scatter) F(pct_beam, energy_mev) F(pct_beam, x0_mm)
   F(pct_job, x_dev) F(pct_job, row_ptr_dev) F(pct_job, cols_dev) F(pct_job, vals_dev)
   F(pct_job, nnz_capacity) F(pct_job, b_dev) F(pct_job, val_dtype) F(pct_job, precision)
+  F(pct_job, chord_mm)
   return 0;
 }
 ''')
@@ -130,7 +132,8 @@ def test_phantom_validation(P, W, field, value, code):
 @pytest.mark.parametrize("field,value", [
     ("n_angles", 0), ("n_protons", -1), ("row_count", 10**9), ("row_begin", -5),
     ("t_range", [1.0, -1.0]), ("sigma_in", -0.1), ("rho", 1.5), ("noise_rel", -0.01),
-    ("step", 0.0), ("path", "spiral"), ("sigma_out", float("inf"))])
+    ("step", 0.0), ("path", "spiral"), ("sigma_out", float("inf")), ("scatter", 7),
+    ("energy_mev", 0.5), ("energy_mev", 2e4), ("x0_mm", 0.0), ("x0_mm", float("nan"))])
 def test_beam_validation(P, W, field, value):
     import copy
     cfg = W.c1()
@@ -140,15 +143,19 @@ def test_beam_validation(P, W, field, value):
         row_count = value
     elif field == "row_begin":
         row_begin = value
-    elif field == "path":
+    elif field in ("path", "scatter"):
         bm["path"] = "straight"
     else:
         bm[field] = value
+        if field in ("energy_mev", "x0_mm"):
+            bm["scatter"] = "highland"
     js = P.JobSet()
     js.add(cfg["phantom"], bm, None, row_begin=row_begin, row_count=row_count)
     n, arr = js.array()
     if field == "path":
         arr[0].beam.contents.path = 9
+    if field == "scatter":
+        arr[0].beam.contents.scatter = value
     assert P.lib().pct_workspace_bytes(n, arr) == 0
     # the entry points reject it on the host, before anything is enqueued
     assert P.lib().pct_count_rows(n, arr, None, 1 << 30, None, None) == -1
@@ -168,6 +175,12 @@ def test_job_validation(P, W):
     arr[0].nnz_capacity = -1
     assert P.lib().pct_workspace_bytes(n, arr) == 0
     arr[0].nnz_capacity = 0
+    for bad in (-1.0, float("nan"), float("inf")):
+        arr[0].chord_mm = bad
+        assert P.lib().pct_workspace_bytes(n, arr) == 0
+    arr[0].chord_mm = 1.0
+    assert P.lib().pct_workspace_bytes(n, arr) > 0
+    arr[0].chord_mm = 0.0
     # emit needs row_ptr; wepl needs b (and x)
     assert P.lib().pct_emit_csr(n, arr, None, 1 << 30, None) == -1
     assert P.lib().pct_wepl(n, arr, None, 1 << 30, None) == -1
