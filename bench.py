@@ -35,6 +35,10 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched (64 uneven jobs, one graph) vs plain single-phantom comparison")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--no-sap", action="store_true", help="skip the SAP reconstruction leg")
+    ap.add_argument("--no-options", action="store_true",
+                    help="skip the Highland-width and constant-chord variants of the path")
+    ap.add_argument("--sap-only", action="store_true", help="only the SAP reconstruction leg")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample size (0: auto)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for HBM byte counters)")
@@ -265,6 +269,64 @@ def batched_vs_single(P, W, steps, warmup, tune):
     return out
 
 
+def sap_leg(P, W, iters=20, n_strings=100, relax=0.1):
+    """SAP (Sec. II-D) on systems emitted on the GPU: the paper's example (m = 20n,
+    200 x 160 pixels: string iterates in LDS) and c1 (400 x 400: iterates in HBM).
+    Timed with HIP events on the stream the kernels run on."""
+    import torch
+    out = {}
+    for name, cfg, k in (("paper", W.c_paper(), iters), ("c1", W.c1(), 2)):
+        o = P.simulate(cfg)
+        n = o["x"].numel()
+        S = P.Sap(o["row_ptr"], o["cols"], o["vals"], o["b"], n, n_strings=n_strings, relax=relax)
+        x = torch.zeros_like(o["x"])
+        S.iterate(x, 1)   # warm-up
+        x.zero_()
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        S.iterate(x, k)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / k
+        if S.status() != P.PCT_OK:
+            raise RuntimeError("SAP device status " + P.status_string(S.status()))
+        m, nnz = o["row_ptr"].numel() - 1, o["nnz"]
+        vb = o["vals"].element_size()
+        # per iteration: A once (cols, vals, row_ptr, b, coefficient), x read by every
+        # string, string iterates written and read back by the average, x written
+        byt = nnz * (4 + vb) + m * (8 + 4 + 4) + 3 * n_strings * n * 4 + n * 4
+        xt = o["x"].double()
+        err = float(torch.linalg.norm(x.double() - xt) / torch.linalg.norm(xt))
+        lds = n * 4 <= 160 * 1024
+        out[name] = {"workload": cfg["name"], "rows": m, "nnz": nnz, "cols": n, "strings": n_strings,
+                     "relax": relax, "iterations": k, "ms_per_iteration": ms,
+                     "row_actions_per_s": m / (ms * 1e-3), "nnz_per_s": nnz / (ms * 1e-3),
+                     "GBps": byt / (ms * 1e-3) / 1e9, "frac_hbm": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "iterate": "LDS" if lds else "HBM", "rel_error_vs_x": err}
+        del S, o, x
+        torch.cuda.empty_cache()
+    return out
+
+
+def options_leg(P, W, steps, warmup):
+    """The path with Highland widths per proton (c1) and with the constant chord length
+    of the paper's example, against their default forms."""
+    import torch
+    out = {}
+    for name, cfg in (("c1_highland", W.c1_highland()), ("paper_const_chord", W.c_paper_const()),
+                      ("paper_exact", W.c_paper())):
+        pl = Pipeline(P, [cfg], "mixed")
+        dt, _ = time_pipeline(pl, steps, warmup)
+        ms = 1e3 * dt / steps
+        out[name] = {"workload": cfg["name"], "protons_per_s": pl.total_rows / (ms * 1e-3), "ms_per_step": ms,
+                     "nnz_per_s": pl.total_nnz / (ms * 1e-3)}
+        del pl
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -288,6 +350,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}))
+        return
+
+    if args.sap_only:
+        print(json.dumps({"sap": sap_leg(P, W)}))
         return
 
     cfgs, chunk = workload(args.workload, W)
@@ -342,6 +408,12 @@ def main():
 
     if not args.no_batched:
         res.update(batched_vs_single(P, W, args.steps, args.warmup, not args.no_tune))
+
+    if not args.no_options:
+        res["options"] = options_leg(P, W, max(3, args.steps // 2), 1)
+
+    if not args.no_sap:
+        res["sap"] = sap_leg(P, W)
 
     if not args.no_cpu:
         target = args.cpu_rows

@@ -228,6 +228,54 @@ pct_status pct_graph_create(int32_t n_jobs, const pct_job *jobs, int32_t build_x
 pct_status pct_graph_launch(pct_graph graph, void *stream);
 pct_status pct_graph_destroy(pct_graph graph);
 
+/* ------------------------------------------------------- reconstruction (Sec. II-D)
+ * String-averaging projections (SAP) on A x = b, the reconstruction the paper runs on
+ * the system the simulator writes.  One iteration from the iterate x_k: the rows, taken
+ * in the order `order_dev` (NULL: 0 .. m-1), are split into M strings of consecutive
+ * positions, string t covering positions [floor(t m / M), floor((t+1) m / M)); every
+ * string starts from y = x_k and applies, row after row,
+ *     y <- y + lambda (b_i - <a_i, y>) / ||a_i||^2 a_i     (rows with ||a_i|| = 0 skipped),
+ * and x_{k+1} = sum_t w_t y_t.  This is the usual Kaczmarz sign with the current y in
+ * the residual; the printed update uses x_k and the opposite sign.
+ * Arithmetic: y in binary32, <a_i, y> and ||a_i||^2 accumulated in binary64, the
+ * weighted sum over strings in binary64 in string order (deterministic). */
+typedef struct {
+    int64_t n_rows;               /* m >= 0 */
+    int32_t n_cols;               /* n >= 1, the length of x */
+    int32_t val_dtype;            /* PCT_F32 | PCT_F16 */
+    int64_t nnz;                  /* length of cols_dev and vals_dev */
+    const int64_t *row_ptr_dev;   /* m + 1 entries, non-decreasing, within [0, nnz] */
+    const int32_t *cols_dev;      /* each in [0, n) */
+    const void *vals_dev;         /* val_dtype */
+    const float *b_dev;           /* m entries */
+} pct_csr;
+
+typedef struct {
+    int32_t n_strings;            /* M >= 1 */
+    float relax;                  /* lambda, 0 < lambda < 2 */
+    const double *weights;        /* host, M entries >= 0 summing to 1 within 1e-9, copied
+                                     by pct_sap_prepare; NULL: 1/M */
+    const int64_t *order_dev;     /* device, m row indices in [0, m); NULL: natural order */
+} pct_sap;
+
+/* Bytes of device workspace for pct_sap_prepare / pct_sap_iterate (0 if a descriptor is
+ * invalid): a status word, one coefficient per row and M x n binary32 string iterates. */
+size_t pct_sap_workspace_bytes(const pct_csr *A, const pct_sap *p);
+
+/* Per-row coefficients lambda / ||a_i||^2 and the weights into the workspace.  Checks
+ * row_ptr, the columns and the order on the device: a row with an out-of-range column or
+ * bounds, or an out-of-range order entry, is skipped by pct_sap_iterate and sets
+ * PCT_EINVAL in the device status word (read it with pct_device_status on this
+ * workspace).  Clears the status word first. */
+pct_status pct_sap_prepare(const pct_csr *A, const pct_sap *p, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* n_iter >= 0 iterations from x_dev (n floats, read and overwritten with the result),
+ * after pct_sap_prepare on the same A, parameters and workspace.  Each string is one
+ * wavefront; its iterate lives in LDS when n binary32 fit a workgroup's LDS, else in the
+ * workspace. */
+pct_status pct_sap_iterate(const pct_csr *A, const pct_sap *p, float *x_dev, int32_t n_iter, void *ws_dev,
+                           size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

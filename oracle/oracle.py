@@ -87,6 +87,8 @@ def lib():
         L.or_hermite.argtypes = [C.POINTER(C.c_double)] * 4 + [C.c_double, C.c_double, C.POINTER(C.c_double)]
         L.or_highland.argtypes = [C.c_double, C.c_double, C.c_double]
         L.or_highland.restype = C.c_double
+        L.or_sap.argtypes = [C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]
         L.or_rsp_at.argtypes = [C.POINTER(Phantom), C.POINTER(C.c_double)]
         L.or_rsp_at.restype = C.c_double
         L.or_phantom_build.argtypes = [C.POINTER(Phantom), C.c_void_p]
@@ -298,3 +300,23 @@ def trace_segments(ph: dict, A, D, lo, hi) -> dict:
     res = lib().or_trace_segments(C.byref(p), len(A), _ptr(A), _ptr(D), _ptr(lo), _ptr(hi))
     out = _collect(res, 1, False)
     return dict(cols=out["cols"], vals=out["vals"], margin=float(out["margin"][0]))
+
+
+def sap(row_ptr, cols, vals, b, n_cols, x0, n_strings=100, relax=0.1, n_iter=1, weights=None,
+        order=None) -> np.ndarray:
+    """String-averaging projections (Sec. II-D) in binary64: n_iter iterations from x0.
+
+    vals and b are taken as given (converted to binary64 exactly); strings are the
+    contiguous blocks floor(t m / M) of the row order."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    m = len(row_ptr) - 1
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    o = None if order is None else np.ascontiguousarray(order, dtype=np.int64)
+    lib().or_sap(m, int(n_cols), _ptr(row_ptr), _ptr(cols), _ptr(vals), _ptr(b), int(n_strings),
+                 float(relax), _ptr(w) if w is not None else None, _ptr(o) if o is not None else None,
+                 _ptr(x), int(n_iter))
+    return x

@@ -23,7 +23,9 @@
  *     voxel [Sec. II-C];
  *   - the WEPL b_i as the inner product of row i with x, optionally with noise
  *     [Sec. II-C];
- *   - optionally, exit-pair widths per proton from Highland's formula [Sec. II-B].
+ *   - optionally, exit-pair widths per proton from Highland's formula [Sec. II-B];
+ *   - the string-averaging projection (SAP) reconstruction that consumes A and b
+ *     [Sec. II-D].
  * Where the paper is silent the readings are those listed in the design notes of the
  * repository (Gaussian relative WEPL noise instead of the PSTAR/Tschalar model, a
  * counter-based Philox4x32-10 generator instead of C rand(), a cubic Hermite curve for
@@ -679,3 +681,44 @@ int32_t or_sizeof_path(void) { return (int32_t)sizeof(or_path); }
 int32_t or_sizeof_region(void) { return (int32_t)sizeof(or_region); }
 int32_t or_sizeof_phantom(void) { return (int32_t)sizeof(or_phantom); }
 int32_t or_sizeof_beam(void) { return (int32_t)sizeof(or_beam); }
+
+/* ------------------------------------------------------- SAP reconstruction [Sec. II-D] */
+/* String-averaging projections on A x = b (A in CSR: m rows, n columns).  One iteration
+ * from the iterate x_k: for every string t (rows order[s_t] .. order[s_{t+1} - 1], with
+ * s_t = floor(t m / M)), y starts at x_k and takes, row by row in string order, the
+ * relaxed projection onto the row's hyperplane
+ *     y <- y + lambda (b_i - <a_i, y>) / ||a_i||^2 a_i     (rows with ||a_i|| = 0 skipped);
+ * the next iterate is the weighted sum x_{k+1} = sum_t w_t y_t.  The update uses the
+ * current y, with the residual b_i - <a_i, y> (the standard Kaczmarz sign; the printed
+ * update has the other sign and x_k in place of y).  Everything in binary64.
+ * weights == NULL: w_t = 1/M.  order == NULL: rows in their natural order. */
+void or_sap(int64_t m, int32_t n, const int64_t *row_ptr, const int32_t *cols, const double *vals,
+            const double *b, int32_t M, double lambda, const double *weights, const int64_t *order,
+            double *x, int32_t n_iter)
+{
+    double *y = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *acc = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int32_t it = 0; it < n_iter; ++it) {
+        for (int32_t j = 0; j < n; ++j) acc[j] = 0.0;
+        for (int32_t t = 0; t < M; ++t) {
+            const int64_t s0 = (int64_t)t * m / M, s1 = (int64_t)(t + 1) * m / M;
+            for (int32_t j = 0; j < n; ++j) y[j] = x[j];
+            for (int64_t s = s0; s < s1; ++s) {
+                const int64_t i = order ? order[s] : s;
+                double dot = 0.0, nrm = 0.0;
+                for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                    dot += vals[e] * y[cols[e]];
+                    nrm += vals[e] * vals[e];
+                }
+                if (nrm == 0.0) continue;
+                const double alpha = lambda * (b[i] - dot) / nrm;
+                for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) y[cols[e]] += alpha * vals[e];
+            }
+            const double w = weights ? weights[t] : 1.0 / (double)M;
+            for (int32_t j = 0; j < n; ++j) acc[j] += w * y[j];
+        }
+        for (int32_t j = 0; j < n; ++j) x[j] = acc[j];
+    }
+    free(y);
+    free(acc);
+}

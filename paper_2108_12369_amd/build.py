@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpct.so")
-SOURCES = [os.path.join(CSRC, "pct.hip")]
+SOURCES = [os.path.join(CSRC, "pct.hip"), os.path.join(CSRC, "sap.hip")]
 HEADERS = [os.path.join(CSRC, "pct_device.h"), os.path.join(CSRC, "pct_wave.h"),
            os.path.join(ROOT, "include", "pct.h")]
 

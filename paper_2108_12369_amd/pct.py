@@ -33,7 +33,8 @@ SCATTER = {"fixed": PCT_SCATTER_FIXED, "highland": PCT_SCATTER_HIGHLAND}
 
 SYMBOLS = ("pct_status_string", "pct_version", "pct_phantom_build", "pct_workspace_bytes",
            "pct_count_rows", "pct_emit_csr", "pct_wepl", "pct_device_status", "pct_set_launch_config",
-           "pct_get_launch_config", "pct_autotune", "pct_graph_create", "pct_graph_launch", "pct_graph_destroy")
+           "pct_get_launch_config", "pct_autotune", "pct_graph_create", "pct_graph_launch", "pct_graph_destroy",
+           "pct_sap_workspace_bytes", "pct_sap_prepare", "pct_sap_iterate")
 
 
 class PctError(RuntimeError):
@@ -68,6 +69,17 @@ class Job(C.Structure):
                 ("row_ptr_dev", C.c_void_p), ("cols_dev", C.c_void_p), ("vals_dev", C.c_void_p),
                 ("nnz_capacity", C.c_int64), ("b_dev", C.c_void_p), ("val_dtype", C.c_int32),
                 ("precision", C.c_int32), ("chord_mm", C.c_double)]
+
+
+class Csr(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("n_cols", C.c_int32), ("val_dtype", C.c_int32), ("nnz", C.c_int64),
+                ("row_ptr_dev", C.c_void_p), ("cols_dev", C.c_void_p), ("vals_dev", C.c_void_p),
+                ("b_dev", C.c_void_p)]
+
+
+class SapParams(C.Structure):
+    _fields_ = [("n_strings", C.c_int32), ("relax", C.c_float), ("weights", C.POINTER(C.c_double)),
+                ("order_dev", C.c_void_p)]
 
 
 class LaunchConfig(C.Structure):
@@ -112,6 +124,13 @@ def lib():
         L.pct_graph_launch.restype = C.c_int32
         L.pct_graph_destroy.argtypes = [C.c_void_p]
         L.pct_graph_destroy.restype = C.c_int32
+        L.pct_sap_workspace_bytes.argtypes = [C.POINTER(Csr), C.POINTER(SapParams)]
+        L.pct_sap_workspace_bytes.restype = C.c_size_t
+        L.pct_sap_prepare.argtypes = [C.POINTER(Csr), C.POINTER(SapParams), C.c_void_p, C.c_size_t, C.c_void_p]
+        L.pct_sap_prepare.restype = C.c_int32
+        L.pct_sap_iterate.argtypes = [C.POINTER(Csr), C.POINTER(SapParams), C.c_void_p, C.c_int32, C.c_void_p,
+                                      C.c_size_t, C.c_void_p]
+        L.pct_sap_iterate.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -354,3 +373,53 @@ def simulate(cfg: dict, row_begin: int = 0, row_count: int | None = None, precis
     _check(st, "device status after pct_emit_csr")
     return {"x": x, "row_ptr": row_ptr, "cols": cols[:nnz], "vals": vals[:nnz], "b": b[:row_count],
             "nnz": nnz}
+
+
+# ------------------------------------------------------------------ SAP reconstruction
+
+class Sap:
+    """pct_sap_prepare / pct_sap_iterate on one CSR system (device tensors).
+
+    row_ptr int64 (m + 1), cols int32, vals float32 or float16, b float32 (m); strings
+    are consecutive blocks of the row order (order: int64 device tensor or None)."""
+
+    def __init__(self, row_ptr, cols, vals, b, n_cols: int, n_strings: int = 100, relax: float = 0.1,
+                 weights=None, order=None, stream=None):
+        self._keep = [row_ptr, cols, vals, b, order]
+        A = Csr()
+        A.n_rows = int(row_ptr.numel()) - 1
+        A.n_cols = int(n_cols)
+        A.val_dtype = PCT_F16 if vals.dtype == torch.float16 else PCT_F32
+        A.nnz = int(cols.numel())
+        A.row_ptr_dev = _ptr(row_ptr)
+        A.cols_dev = _ptr(cols)
+        A.vals_dev = _ptr(vals)
+        A.b_dev = _ptr(b)
+        p = SapParams()
+        p.n_strings = int(n_strings)
+        p.relax = float(relax)
+        self._w = None
+        if weights is not None:
+            self._w = (C.c_double * len(weights))(*[float(v) for v in weights])
+            p.weights = C.cast(self._w, C.POINTER(C.c_double))
+        p.order_dev = _ptr(order)
+        self.A, self.p = A, p
+        nb = int(lib().pct_sap_workspace_bytes(C.byref(A), C.byref(p)))
+        if nb == 0:
+            raise PctError(PCT_EINVAL, "pct_sap_workspace_bytes")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=row_ptr.device)
+        self.prepare(stream)
+
+    def prepare(self, stream=None):
+        _check(lib().pct_sap_prepare(C.byref(self.A), C.byref(self.p), _ptr(self.ws), self.ws.numel(),
+                                     _stream_ptr(stream)), "pct_sap_prepare")
+
+    def iterate(self, x: torch.Tensor, n_iter: int = 1, stream=None) -> torch.Tensor:
+        """n_iter iterations in place on x (float32 device tensor of n_cols)."""
+        assert x.dtype == torch.float32 and x.numel() == self.A.n_cols and x.is_contiguous()
+        _check(lib().pct_sap_iterate(C.byref(self.A), C.byref(self.p), _ptr(x), int(n_iter), _ptr(self.ws),
+                                     self.ws.numel(), _stream_ptr(stream)), "pct_sap_iterate")
+        return x
+
+    def status(self, stream=None) -> int:
+        return device_status(self.ws, stream)

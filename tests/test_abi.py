@@ -59,6 +59,10 @@ int main(void) {
   F(pct_job, x_dev) F(pct_job, row_ptr_dev) F(pct_job, cols_dev) F(pct_job, vals_dev)
   F(pct_job, nnz_capacity) F(pct_job, b_dev) F(pct_job, val_dtype) F(pct_job, precision)
   F(pct_job, chord_mm)
+  printf("pct_csr %zu\npct_sap %zu\n", sizeof(pct_csr), sizeof(pct_sap));
+  F(pct_csr, n_cols) F(pct_csr, val_dtype) F(pct_csr, nnz) F(pct_csr, row_ptr_dev) F(pct_csr, cols_dev)
+  F(pct_csr, vals_dev) F(pct_csr, b_dev)
+  F(pct_sap, relax) F(pct_sap, weights) F(pct_sap, order_dev)
   return 0;
 }
 ''')
@@ -66,7 +70,8 @@ int main(void) {
     subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     got = dict(line.split() for line in out if line.strip())
-    types = {"pct_region": P.Region, "pct_phantom": P.Phantom, "pct_beam": P.Beam, "pct_job": P.Job}
+    types = {"pct_region": P.Region, "pct_phantom": P.Phantom, "pct_beam": P.Beam, "pct_job": P.Job,
+             "pct_csr": P.Csr, "pct_sap": P.SapParams}
     for k, v in got.items():
         if "." in k:
             t, m = k.split(".")
@@ -259,3 +264,38 @@ def test_graph_and_autotune_validate_on_host(P, W):
     assert lib.pct_graph_create(n, arr, 0, None, 1 << 30, C.c_void_p(1 << 20), C.byref(h)) == -1
     assert lib.pct_graph_launch(None, None) == -1
     assert lib.pct_graph_destroy(None) == 0
+
+
+def test_sap_validation_on_host(P):
+    """Descriptor checks of the SAP entry points happen before any launch."""
+    A = P.Csr(n_rows=10, n_cols=5, val_dtype=0, nnz=30, row_ptr_dev=1 << 20, cols_dev=1 << 21,
+              vals_dev=1 << 22, b_dev=1 << 23)
+    p = P.SapParams(n_strings=3, relax=0.5)
+    L = P.lib()
+    need = L.pct_sap_workspace_bytes(C.byref(A), C.byref(p))
+    # header + 10 coefficients + 3 weights + 3 x 5 string iterates, 256-byte aligned parts
+    assert need == 256 + 256 + 256 + 3 * 5 * 4
+    for field, bad in (("n_cols", 0), ("n_rows", -1), ("val_dtype", 7), ("nnz", -1)):
+        B = P.Csr.from_buffer_copy(A)
+        setattr(B, field, bad)
+        assert L.pct_sap_workspace_bytes(C.byref(B), C.byref(p)) == 0, field
+    for relax in (0.0, 2.0, -1.0, float("nan")):
+        q = P.SapParams(n_strings=3, relax=relax)
+        assert L.pct_sap_workspace_bytes(C.byref(A), C.byref(q)) == 0
+    assert L.pct_sap_workspace_bytes(C.byref(A), C.byref(P.SapParams(n_strings=0, relax=0.5))) == 0
+    for w in ([0.5, 0.5, 0.5], [1.0, 0.5, -0.5], [float("nan"), 0.5, 0.5]):
+        arr = (C.c_double * 3)(*w)
+        q = P.SapParams(n_strings=3, relax=0.5, weights=C.cast(arr, C.POINTER(C.c_double)))
+        assert L.pct_sap_workspace_bytes(C.byref(A), C.byref(q)) == 0
+    arr = (C.c_double * 3)(0.2, 0.3, 0.5)
+    q = P.SapParams(n_strings=3, relax=0.5, weights=C.cast(arr, C.POINTER(C.c_double)))
+    assert L.pct_sap_workspace_bytes(C.byref(A), C.byref(q)) == need
+    # missing or short workspace, bad iteration count: refused on the host
+    assert L.pct_sap_prepare(C.byref(A), C.byref(p), None, need, None) == -4
+    assert L.pct_sap_prepare(C.byref(A), C.byref(p), C.c_void_p(1 << 20), need - 1, None) == -4
+    assert L.pct_sap_iterate(C.byref(A), C.byref(p), C.c_void_p(1 << 24), -1, C.c_void_p(1 << 20), need,
+                             None) == -1
+    assert L.pct_sap_iterate(C.byref(A), C.byref(p), None, 1, C.c_void_p(1 << 20), need, None) == -1
+    B = P.Csr.from_buffer_copy(A)
+    B.b_dev = None
+    assert L.pct_sap_prepare(C.byref(B), C.byref(p), C.c_void_p(1 << 20), need, None) == -1

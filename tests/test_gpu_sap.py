@@ -1,0 +1,170 @@
+"""SAP reconstruction (Sec. II-D) on the GPU through the C ABI, against the oracle.
+
+Inputs: systems built by the oracle's own traversal (binary64 lengths and WEPL rounded
+once to binary32, or to binary16 for the values), handed unchanged to both sides.
+
+Bar: the GPU keeps y in binary32 and sums in binary64; one row update rounds y[c] once
+(relative 2^-24) and a voxel takes a few updates per row block, so after K iterations
+the deviation from the binary64 oracle stays near K * 1e-7 of the largest RSP.  The
+tests allow 1e-5 (K <= 2) and 1e-4 (K = 20) of max|x|, plus 1e-6 absolute.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2108_12369_amd import pct
+    pct.lib()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return pct
+
+
+def _system(oracle, W, ph, bm, val_dtype="f32"):
+    o = oracle.run(W.workload("sap-input", ph, bm))
+    vt = np.float16 if val_dtype == "f16" else np.float32
+    vals = o["vals"].astype(np.float32).astype(vt)
+    b = o["b"].astype(np.float32)
+    return dict(row_ptr=o["row_ptr"], cols=o["cols"], vals=vals, b=b, x_true=o["x"], n=len(o["x"]))
+
+
+def _to_dev(sysd):
+    dev = "cuda"
+    return (torch.as_tensor(sysd["row_ptr"], device=dev), torch.as_tensor(sysd["cols"], device=dev),
+            torch.as_tensor(sysd["vals"], device=dev), torch.as_tensor(sysd["b"], device=dev))
+
+
+def _gpu_sap(P, sysd, x0, n_iter, **kw):
+    rp, c, v, b = _to_dev(sysd)
+    order = kw.pop("order", None)
+    if order is not None:
+        order = torch.as_tensor(order, dtype=torch.int64, device="cuda")
+    S = P.Sap(rp, c, v, b, sysd["n"], order=order, **kw)
+    x = torch.as_tensor(np.asarray(x0, dtype=np.float32), device="cuda").clone()
+    S.iterate(x, n_iter)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), S.status()
+
+
+def _oracle_sap(oracle, sysd, x0, n_iter, **kw):
+    return oracle.sap(sysd["row_ptr"], sysd["cols"], sysd["vals"].astype(np.float64),
+                      sysd["b"].astype(np.float64), sysd["n"], np.asarray(x0, dtype=np.float64),
+                      n_iter=n_iter, **kw)
+
+
+def _close(got, want, rel):
+    scale = max(float(np.abs(want).max()), 1e-30)
+    err = float(np.abs(got.astype(np.float64) - want).max())
+    print("max err", err, "scale", scale, flush=True)
+    assert err <= rel * scale + 1e-6, (err, scale)
+
+
+def _paper_sys(oracle, W, m_mult=5, val_dtype="f32"):
+    cfg = W.c_paper()
+    bm = dict(cfg["beam"], n_protons=32000 * m_mult)
+    return _system(oracle, W, cfg["phantom"], bm, val_dtype)
+
+
+def test_sap_lds_path_paper_grid(P, oracle, W):
+    """200 x 160 pixels (the iterate fits in LDS), m = 5n, M = 100, lambda = 0.1."""
+    s = _paper_sys(oracle, W, 5)
+    x0 = np.zeros(s["n"])
+    for K in (1, 2):
+        got, st = _gpu_sap(P, s, x0, K, n_strings=100, relax=0.1)
+        assert st == 0
+        _close(got, _oracle_sap(oracle, s, x0, K, n_strings=100, relax=0.1), 1e-5)
+
+
+def test_sap_fp16_values(P, oracle, W):
+    s = _paper_sys(oracle, W, 2, "f16")
+    x0 = np.full(s["n"], 0.5)
+    got, st = _gpu_sap(P, s, x0, 2, n_strings=100, relax=0.2)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, s, x0, 2, n_strings=100, relax=0.2), 1e-5)
+
+
+def test_sap_workspace_path_large_grid(P, oracle, W):
+    """256 x 256 pixels: more than one workgroup's LDS, the iterate lives in HBM."""
+    ph = W.phantom(2, (256, 256), (0.8, 0.8), W.neo1_regions())
+    bm = W.beam(555, 60, 3.0, 12000, (-102.4, 102.4), path="hermite", sigma_in=0.01, sigma_out=0.01,
+                sigma_lat=1.0, step=0.4)
+    s = _system(oracle, W, ph, bm)
+    assert s["n"] * 4 > 160 * 1024
+    x0 = np.zeros(s["n"])
+    got, st = _gpu_sap(P, s, x0, 2, n_strings=50, relax=0.3)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, s, x0, 2, n_strings=50, relax=0.3), 1e-5)
+
+
+def test_sap_order_weights_and_ragged_strings(P, oracle, W):
+    ph = W.phantom(2, (64, 48), (3.0, 3.0), W.neo1_regions())
+    bm = W.beam(556, 30, 6.0, 3001, (-100.0, 100.0))
+    s = _system(oracle, W, ph, bm)
+    rng = np.random.default_rng(3)
+    order = rng.permutation(3001)
+    w = rng.uniform(0.1, 1.0, 7)
+    w /= w.sum()
+    x0 = rng.uniform(0, 1, s["n"])
+    got, st = _gpu_sap(P, s, x0, 3, n_strings=7, relax=1.3, weights=list(w), order=order)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, s, x0, 3, n_strings=7, relax=1.3, weights=w, order=order), 1e-5)
+
+
+def test_sap_edge_cases(P, oracle, W):
+    ph = W.phantom(2, (32, 32), (6.0, 6.0), W.neo1_regions())
+    # offsets beyond the grid: many empty rows (zero norm, skipped)
+    bm = W.beam(557, 10, 36.0, 300, (-200.0, 200.0))
+    s = _system(oracle, W, ph, bm)
+    assert (np.diff(s["row_ptr"]) == 0).any()
+    x0 = np.linspace(0, 1, s["n"])
+    for M in (1, 300, 1000):   # one chain, one row per string, more strings than rows
+        got, st = _gpu_sap(P, s, x0, 2, n_strings=M, relax=0.9)
+        assert st == 0
+        _close(got, _oracle_sap(oracle, s, x0, 2, n_strings=M, relax=0.9), 1e-5)
+    got, st = _gpu_sap(P, s, x0, 0, n_strings=5, relax=0.9)
+    assert np.array_equal(got, x0.astype(np.float32))
+
+
+def test_sap_bad_column_is_reported_and_skipped(P, oracle, W):
+    ph = W.phantom(2, (32, 32), (6.0, 6.0), W.neo1_regions())
+    bm = W.beam(558, 10, 36.0, 200, (-90.0, 90.0))
+    s = _system(oracle, W, ph, bm)
+    bad_row = int(np.argmax(np.diff(s["row_ptr"])))
+    s_bad = dict(s, cols=s["cols"].copy())
+    s_bad["cols"][s["row_ptr"][bad_row]] = s["n"] + 5
+    x0 = np.zeros(s["n"])
+    got, st = _gpu_sap(P, s_bad, x0, 1, n_strings=4, relax=0.5)
+    assert st == P.PCT_EINVAL
+    keep = np.array([i for i in range(200) if i != bad_row])
+    # the flagged row is skipped: same as the system without it, in a string of its own
+    # position (strings keep their row ranges)
+    want = _oracle_sap(oracle, dict(s, b=np.where(np.arange(200) == bad_row, 0.0, s["b"]).astype(np.float32),
+                                    vals=np.where(np.repeat(np.arange(200), np.diff(s["row_ptr"])) == bad_row, 0.0,
+                                                  s["vals"]).astype(np.float32)), x0, 1, n_strings=4, relax=0.5)
+    _close(got, want, 1e-5)
+    assert len(keep) == 199
+
+
+def test_sap_reconstructs_emitted_system(P, oracle, W):
+    """GPU emit -> GPU SAP, 20 iterations, on the paper's example (m = 20n, straight,
+    lambda = 0.1, M = 100): close to the oracle's own pipeline, and approaching x."""
+    cfg = W.c_paper()
+    out = P.simulate(cfg)
+    S = P.Sap(out["row_ptr"], out["cols"], out["vals"], out["b"], out["x"].numel(), n_strings=100, relax=0.1)
+    x = torch.zeros_like(out["x"])
+    errs = []
+    xt = out["x"].double()
+    for _ in range(4):
+        S.iterate(x, 5)
+        errs.append(float(torch.linalg.norm(x.double() - xt) / torch.linalg.norm(xt)))
+    assert S.status() == 0
+    print("relative error after 5/10/15/20 iterations", errs, flush=True)
+    assert all(errs[i + 1] < errs[i] for i in range(3))
+    o = oracle.run(cfg)
+    want = oracle.sap(o["row_ptr"], o["cols"], o["vals"].astype(np.float32).astype(np.float64),
+                      o["b"].astype(np.float32).astype(np.float64), len(o["x"]), np.zeros(len(o["x"])),
+                      n_strings=100, relax=0.1, n_iter=20)
+    _close(x.cpu().numpy(), want, 1e-4)
