@@ -46,6 +46,8 @@ typedef int32_t pct_status;
 
 #define PCT_CORNER_AVG 0   /* pixel value = mean RSP at its 4 (8) corners (Sec. II-A)       */
 #define PCT_CENTER     1   /* pixel value = RSP at its center point (Sec. II-A)             */
+#define PCT_AREA_AVG   2   /* pixel value = sum of region RSP x area (volume) fraction      */
+                           /* (Sec. II-A), the fractions from area_samples^dim midpoints    */
 
 #define PCT_STRAIGHT   0   /* straight-line proton paths (Sec. II-B)                        */
 #define PCT_HERMITE    1   /* cubic spline between entry and exit, straight outside (II-B)  */
@@ -61,15 +63,18 @@ typedef int32_t pct_status;
 
 #define PCT_MAX_REGIONS 16
 
-/* One region of a non-homogeneous ellipse object (Sec. II-A).  A point belongs to the
- * region when sum(((p - center) / semi)^2) <= 1 over x, y (and z for an ellipsoid in
- * 3D).  Regions are painted in array order: a later region replaces the RSP of an
- * earlier one.  Region 0 is the outer boundary used for the proton entry and exit. */
+/* One region of a non-homogeneous ellipse object (Sec. II-A).  A point p belongs to
+ * the region when sum((u / semi)^2) <= 1, u = p - center turned by -angle_deg about z
+ * (u_x = c d_x + s d_y, u_y = -s d_x + c d_y with c, s the cosine and sine of the angle,
+ * d = p - center), over x, y (and z for an ellipsoid in 3D).  Regions are painted in
+ * array order: a later region replaces the RSP of an earlier one.  Region 0 is the outer
+ * boundary used for the proton entry and exit. */
 typedef struct {
     int32_t shape;      /* PCT_ELLIPSE | PCT_ELLIPSOID */
     float rsp;          /* relative stopping power, >= 0 */
     double center[3];   /* mm */
     double semi[3];     /* semi-axes, mm, > 0 (z ignored unless ellipsoid in 3D) */
+    double angle_deg;   /* rotation of the semi-axes in the x-y plane, counterclockwise */
 } pct_region;
 
 /* Voxel grid and phantom (Sec. II-A).  Voxel (ix, iy, iz) covers
@@ -81,8 +86,9 @@ typedef struct {
     double h[3];                 /* voxel size, mm, > 0 */
     double origin[3];            /* lower corner of the grid box, mm */
     int32_t n_regions;           /* 1..PCT_MAX_REGIONS */
-    int32_t voxelize;            /* PCT_CORNER_AVG | PCT_CENTER */
+    int32_t voxelize;            /* PCT_CORNER_AVG | PCT_CENTER | PCT_AREA_AVG */
     const pct_region *regions;   /* host array of n_regions */
+    int32_t area_samples;        /* PCT_AREA_AVG: midpoints per axis, 1..64 (0: 8) */
 } pct_phantom;
 
 /* Parallel beam and proton source (Sec. II-B).  Proton g (0 <= g < n_protons) belongs
@@ -148,10 +154,13 @@ const char *pct_status_string(pct_status status);
 /* Library version, major*10000 + minor*100 + patch. */
 int32_t pct_version(void);
 
-/* Voxelise the phantom into x_dev (n[0]*n[1]*(dim==3 ? n[2] : 1) floats) with the
- * pixel-value rule of Sec. II-A: the RSP at the voxel center, or the mean of the RSP at
- * its 4 (2D) or 8 (3D) corners; the point tests are done in binary64 and the value is
- * rounded once to binary32. */
+/* Voxelise the phantom into x_dev (n[0]*n[1]*(dim==3 ? n[2] : 1) floats) with a
+ * pixel-value rule of Sec. II-A: the RSP at the voxel center; the mean of the RSP at its
+ * 4 (2D) or 8 (3D) corners; or the weighted-area average, the mean RSP over the
+ * S^dim points ((i + 1/2) / S of the voxel per axis, S = area_samples), which is
+ * sum_r RSP_r x (fraction of the points in region r) and tends to the exact area
+ * fractions as S grows.  The point tests are done in binary64 and the value is rounded
+ * once to binary32. */
 pct_status pct_phantom_build(const pct_phantom *phantom, float *x_dev, void *stream);
 
 /* Bytes of device workspace that pct_count_rows / pct_emit_csr / pct_wepl need for

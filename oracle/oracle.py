@@ -18,7 +18,7 @@ _SRC = os.path.join(_HERE, "pct_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SHAPES = {"ellipse": 0, "ellipsoid": 1}
-VOXELIZE = {"corner_avg": 0, "center": 1}
+VOXELIZE = {"corner_avg": 0, "center": 1, "area_avg": 2}
 PATHS = {"straight": 0, "hermite": 1}
 KIND_MISS_GRID, KIND_STRAIGHT, KIND_CURVED, KIND_STRAIGHT_FALLBACK = 0, 1, 2, 3
 
@@ -35,13 +35,13 @@ def build(force: bool = True) -> str:
 
 class Region(C.Structure):
     _fields_ = [("shape", C.c_int32), ("center", C.c_double * 3), ("semi", C.c_double * 3),
-                ("rsp", C.c_float)]
+                ("rsp", C.c_float), ("angle_deg", C.c_double)]
 
 
 class Phantom(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double * 3),
                 ("origin", C.c_double * 3), ("n_regions", C.c_int32),
-                ("regions", C.POINTER(Region)), ("voxelize", C.c_int32)]
+                ("regions", C.POINTER(Region)), ("voxelize", C.c_int32), ("area_samples", C.c_int32)]
 
 
 class Beam(C.Structure):
@@ -124,6 +124,7 @@ def make_phantom(ph: dict):
         arr[i].center[:] = [float(v) for v in c]
         arr[i].semi[:] = [float(v) for v in s]
         arr[i].rsp = float(r["rsp"])
+        arr[i].angle_deg = float(r.get("angle_deg", 0.0))
     p = Phantom()
     dim = int(ph["dim"])
     n = list(ph["n"]) + [1] * (3 - len(ph["n"]))
@@ -139,6 +140,7 @@ def make_phantom(ph: dict):
     p.n_regions = len(regs)
     p.regions = C.cast(arr, C.POINTER(Region))
     p.voxelize = VOXELIZE[ph.get("voxelize", "corner_avg")]
+    p.area_samples = int(ph.get("area_samples") or 8)
     return p, arr
 
 

@@ -50,7 +50,7 @@
 /* ------------------------------------------------------------------ public structs */
 
 enum { OR_ELLIPSE = 0, OR_ELLIPSOID = 1 };          /* ellipse ignores z (cylinder in 3D) */
-enum { OR_CORNER_AVG = 0, OR_CENTER = 1 };
+enum { OR_CORNER_AVG = 0, OR_CENTER = 1, OR_AREA_AVG = 2 };
 enum { OR_STRAIGHT = 0, OR_HERMITE = 1 };
 enum { OR_KIND_MISS_GRID = 0, OR_KIND_STRAIGHT = 1, OR_KIND_CURVED = 2,
        OR_KIND_STRAIGHT_FALLBACK = 3 };
@@ -60,6 +60,7 @@ typedef struct {
     double center[3];
     double semi[3];
     float rsp;
+    double angle_deg;       /* semi-axes turned counterclockwise in the x-y plane */
 } or_region;
 
 typedef struct {
@@ -70,6 +71,7 @@ typedef struct {
     int32_t n_regions;
     const or_region *regions;  /* painter's order, region 0 is the outer boundary */
     int32_t voxelize;
+    int32_t area_samples;      /* weighted-area rule: midpoints per axis */
 } or_phantom;
 
 typedef struct {
@@ -192,17 +194,36 @@ static void normalize3(double v[3])
 /* Line Q + l d against the outer boundary (region 0) [Sec. II-B entry and exit points].
  * Returns 1 on a hit with l1 < l2.  *half_chord (mm) is sqrt(|disc|)/a * |d|: how far
  * the line is from being tangent (imaginary for a miss). */
+/* A vector expressed in the frame of a region's turned semi-axes: rotation by minus the
+ * region's angle in the x-y plane (z unchanged). */
+static void to_region_frame(const or_region *r, const double v[3], double u[3])
+{
+    u[0] = v[0];
+    u[1] = v[1];
+    u[2] = v[2];
+    if (r->angle_deg != 0.0) {
+        const double ang = r->angle_deg * (3.14159265358979323846 / 180.0);
+        const double c = cos(ang), s = sin(ang);
+        u[0] = c * v[0] + s * v[1];
+        u[1] = c * v[1] - s * v[0];
+    }
+}
+
 int or_boundary_hit(const or_phantom *ph, const double Q[3], const double d[3],
                     double *l1, double *l2, double *half_chord)
 {
     const or_region *r = &ph->regions[0];
     const int naxes = (r->shape == OR_ELLIPSOID && ph->dim == 3) ? 3 : 2;
     double a = 0.0, b = 0.0, c = -1.0;
+    const double qc[3] = {Q[0] - r->center[0], Q[1] - r->center[1], Q[2] - r->center[2]};
+    double qr[3], dr[3];
+    to_region_frame(r, qc, qr);
+    to_region_frame(r, d, dr);
     for (int i = 0; i < naxes; ++i) {
-        const double q = Q[i] - r->center[i];
+        const double q = qr[i];
         const double s2 = r->semi[i] * r->semi[i];
-        a += d[i] * d[i] / s2;
-        b += q * d[i] / s2;
+        a += dr[i] * dr[i] / s2;
+        b += q * dr[i] / s2;
         c += q * q / s2;
     }
     const double disc = b * b - a * c;
@@ -236,9 +257,12 @@ void or_hermite(const double P0[3], const double d0[3], const double P1[3], cons
 static int region_contains(const or_region *r, int dim, const double p[3])
 {
     const int naxes = (r->shape == OR_ELLIPSOID && dim == 3) ? 3 : 2;
+    const double v[3] = {p[0] - r->center[0], p[1] - r->center[1], p[2] - r->center[2]};
+    double w[3];
+    to_region_frame(r, v, w);
     double q = 0.0;
     for (int i = 0; i < naxes; ++i) {
-        const double u = (p[i] - r->center[i]) / r->semi[i];
+        const double u = w[i] / r->semi[i];
         q += u * u;
     }
     return q <= 1.0;
@@ -262,7 +286,24 @@ void or_phantom_build(const or_phantom *ph, float *x)
             for (int ix = 0; ix < ph->n[0]; ++ix) {
                 const int idx[3] = {ix, iy, iz};
                 double val = 0.0;
-                if (ph->voxelize == OR_CENTER) {
+                if (ph->voxelize == OR_AREA_AVG) {
+                    /* weighted-area average: each region's RSP times the fraction of the
+                     * voxel it covers (painter's order), the fractions taken over S^dim
+                     * midpoints (i + 1/2) / S per axis */
+                    const int S = ph->area_samples;
+                    const int sz = (ph->dim == 3) ? S : 1;
+                    double sum = 0.0;
+                    for (int kz = 0; kz < sz; ++kz)
+                        for (int ky = 0; ky < S; ++ky)
+                            for (int kx = 0; kx < S; ++kx) {
+                                const int k[3] = {kx, ky, kz};
+                                double p[3] = {0, 0, 0};
+                                for (int d = 0; d < ph->dim; ++d)
+                                    p[d] = ph->origin[d] + ((double)idx[d] + ((double)k[d] + 0.5) / (double)S) * ph->h[d];
+                                sum += or_rsp_at(ph, p);
+                            }
+                    val = sum / ((double)S * (double)S * (double)sz);
+                } else if (ph->voxelize == OR_CENTER) {
                     double p[3] = {0, 0, 0};
                     for (int d = 0; d < ph->dim; ++d)
                         p[d] = ph->origin[d] + ((double)idx[d] + 0.5) * ph->h[d];

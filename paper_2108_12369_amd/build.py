@@ -37,7 +37,8 @@ def source_digest() -> str:
     """Short SHA-256 over the device sources, the public header and the compiler flags:
     identifies the kernels a stored profile was taken from."""
     import hashlib
-    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                   if f.endswith((".hip", ".h")) and f != "sap.hip")
     files += [os.path.join(ROOT, "include", "pct.h")]
     h = hashlib.sha256(" ".join(FLAGS).encode())
     for f in files:

@@ -273,27 +273,73 @@ __global__ void __launch_bounds__(TILE) k_emit_lane(const JobDev *__restrict__ j
 struct RegionDev {
     int32_t axes;   // 2: ellipse / cylinder, 3: ellipsoid
     float rsp;
+    int32_t rot, pad;
     double c[3], s[3];
+    double cr, sr;   // cosine and sine of the region's angle
+    double hw[2];    // half-widths of its bounding box in x and y
 };
 struct PhantomArgs {
-    int32_t dim, voxelize, n_regions, pad;
+    int32_t dim, voxelize, n_regions, samples;
     int32_t n[3];
     double h[3], o[3];
     RegionDev reg[PCT_MAX_REGIONS];
 };
 
+// sum over the region's axes of (u_i / s_i)^2, u = p - c turned by minus the angle
+__device__ __forceinline__ double region_q(const RegionDev &g, const double p[3]) {
+    double d[3] = {p[0] - g.c[0], p[1] - g.c[1], p[2] - g.c[2]};
+    if (g.rot) {
+        const double u0 = g.cr * d[0] + g.sr * d[1];
+        const double u1 = g.cr * d[1] - g.sr * d[0];
+        d[0] = u0;
+        d[1] = u1;
+    }
+    double q = 0.0;
+    for (int i = 0; i < g.axes; ++i) {
+        const double u = d[i] / g.s[i];
+        q += u * u;
+    }
+    return q;
+}
+
 __device__ __forceinline__ double rsp_at(const PhantomArgs &A, const double p[3]) {
     double v = 0.0;
-    for (int k = 0; k < A.n_regions; ++k) {
-        const RegionDev &g = A.reg[k];
-        double q = 0.0;
-        for (int i = 0; i < g.axes; ++i) {
-            const double u = (p[i] - g.c[i]) / g.s[i];
-            q += u * u;
-        }
-        if (q <= 1.0) v = (double)g.rsp;
-    }
+    for (int k = 0; k < A.n_regions; ++k)
+        if (region_q(A.reg[k], p) <= 1.0) v = (double)A.reg[k].rsp;
     return v;
+}
+
+// Whether region g certainly contains (+1) or certainly misses (-1) every point of the
+// box [lo, hi], with a margin of 1e-9 in q; 0 if the box may meet its boundary.
+__device__ __forceinline__ int region_box(const RegionDev &g, const double lo[3], const double hi[3]) {
+    constexpr double EPS = 1e-9;
+    if (!g.rot) {
+        double qmin = 0.0, qmax = 0.0;
+        for (int i = 0; i < g.axes; ++i) {
+            const double a = (lo[i] - g.c[i]) / g.s[i], b = (hi[i] - g.c[i]) / g.s[i];
+            const double near = (a > 0.0) ? a : ((b < 0.0) ? b : 0.0);
+            qmin += near * near;
+            qmax += fmax(a * a, b * b);
+        }
+        if (qmax < 1.0 - EPS) return 1;
+        if (qmin > 1.0 + EPS) return -1;
+        return 0;
+    }
+    // turned ellipse: convex, so inside if every corner is; outside if the box misses
+    // its bounding box (by a margin)
+    bool all_in = true;
+    const int nc = 1 << g.axes;
+    for (int c = 0; c < nc; ++c) {
+        double p[3];
+        for (int i = 0; i < 3; ++i) p[i] = ((c >> i) & 1) ? hi[i] : lo[i];
+        all_in = all_in && region_q(g, p) < 1.0 - EPS;
+    }
+    if (all_in) return 1;
+    const double m = EPS * (g.s[0] + g.s[1]);
+    bool out = false;
+    for (int i = 0; i < 2; ++i) out = out || lo[i] > g.c[i] + g.hw[i] + m || hi[i] < g.c[i] - g.hw[i] - m;
+    if (g.axes == 3) out = out || lo[2] > g.c[2] + g.s[2] * (1.0 + EPS) || hi[2] < g.c[2] - g.s[2] * (1.0 + EPS);
+    return out ? -1 : 0;
 }
 
 __global__ void __launch_bounds__(256) k_phantom(PhantomArgs A, float *__restrict__ x, int64_t nvox) {
@@ -304,7 +350,41 @@ __global__ void __launch_bounds__(256) k_phantom(PhantomArgs A, float *__restric
     idx[1] = (int)((j / A.n[0]) % A.n[1]);
     idx[2] = (int)(j / ((int64_t)A.n[0] * A.n[1]));
     double val;
-    if (A.voxelize == PCT_CENTER) {
+    if (A.voxelize == PCT_AREA_AVG) {
+        // weighted-area average: the mean RSP over S^dim midpoints of the voxel; a voxel
+        // that no region boundary meets takes the one RSP all of them would give
+        double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < A.dim; ++d) {
+            lo[d] = A.o[d] + (double)idx[d] * A.h[d];
+            hi[d] = A.o[d] + (double)(idx[d] + 1) * A.h[d];
+        }
+        bool uniform = true;
+        double v = 0.0;
+        for (int k = 0; k < A.n_regions; ++k) {
+            const int st = region_box(A.reg[k], lo, hi);
+            uniform = uniform && st != 0;
+            if (st > 0) v = (double)A.reg[k].rsp;
+        }
+        if (uniform) {
+            val = v;
+        } else {
+            const int S = A.samples;
+            const int nz = A.dim == 3 ? S : 1;
+            double sum = 0.0;
+            for (int iz = 0; iz < nz; ++iz)
+                for (int iy = 0; iy < S; ++iy)
+                    for (int ix = 0; ix < S; ++ix) {
+                        const int ii[3] = {ix, iy, iz};
+                        double p[3] = {0.0, 0.0, 0.0};
+                        for (int d = 0; d < A.dim; ++d) {
+                            const double t = ((double)ii[d] + 0.5) / (double)S;
+                            p[d] = A.o[d] + ((double)idx[d] + t) * A.h[d];
+                        }
+                        sum += rsp_at(A, p);
+                    }
+            val = sum / ((double)S * (double)S * (double)nz);
+        }
+    } else if (A.voxelize == PCT_CENTER) {
         double p[3] = {0.0, 0.0, 0.0};
         for (int d = 0; d < A.dim; ++d) p[d] = A.o[d] + ((double)idx[d] + 0.5) * A.h[d];
         val = rsp_at(A, p);
@@ -329,7 +409,9 @@ static pct_status check_phantom(const pct_phantom *ph) {
     if (!ph) return PCT_EINVAL;
     if (ph->dim != 2 && ph->dim != 3) return PCT_EINVAL;
     if (ph->n_regions < 1 || ph->n_regions > PCT_MAX_REGIONS || !ph->regions) return PCT_EINVAL;
-    if (ph->voxelize != PCT_CORNER_AVG && ph->voxelize != PCT_CENTER) return PCT_EINVAL;
+    if (ph->voxelize != PCT_CORNER_AVG && ph->voxelize != PCT_CENTER && ph->voxelize != PCT_AREA_AVG)
+        return PCT_EINVAL;
+    if (ph->voxelize == PCT_AREA_AVG && (ph->area_samples < 0 || ph->area_samples > 64)) return PCT_EINVAL;
     int64_t nv = 1;
     for (int d = 0; d < ph->dim; ++d) {
         if (ph->n[d] < 1) return PCT_EINVAL;
@@ -345,6 +427,7 @@ static pct_status check_phantom(const pct_phantom *ph) {
         for (int i = 0; i < na; ++i) {
             if (!(r.semi[i] > 0.0) || !finite_d(r.semi[i]) || !finite_d(r.center[i])) return PCT_EINVAL;
         }
+        if (!finite_d(r.angle_deg) || fabs(r.angle_deg) > 360.0) return PCT_EINVAL;
     }
     return PCT_OK;
 }
@@ -431,6 +514,10 @@ static JobDev make_job(const pct_job &jb, int64_t count_off, int64_t tile_base) 
         J.oc[d] = o.center[d];
         J.inv_s2[d] = (d < J.outer_axes) ? 1.0 / (o.semi[d] * o.semi[d]) : 0.0;
     }
+    J.orot_on = o.angle_deg != 0.0 ? 1 : 0;
+    const double oang = o.angle_deg * (3.14159265358979323846 / 180.0);
+    J.orot[0] = J.orot_on ? cos(oang) : 1.0;
+    J.orot[1] = J.orot_on ? sin(oang) : 0.0;
     J.K = bm.n_angles;
     J.seed = bm.seed;
     J.angle0 = bm.angle0_deg;
@@ -587,6 +674,7 @@ pct_status pct_phantom_build(const pct_phantom *ph, float *x_dev, void *stream) 
     A.dim = ph->dim;
     A.voxelize = ph->voxelize;
     A.n_regions = ph->n_regions;
+    A.samples = ph->area_samples > 0 ? ph->area_samples : 8;
     for (int d = 0; d < 3; ++d) {
         A.n[d] = d < ph->dim ? ph->n[d] : 1;
         A.h[d] = d < ph->dim ? ph->h[d] : 1.0;
@@ -600,6 +688,13 @@ pct_status pct_phantom_build(const pct_phantom *ph, float *x_dev, void *stream) 
             A.reg[k].c[i] = r.center[i];
             A.reg[k].s[i] = r.semi[i];
         }
+        A.reg[k].rot = r.angle_deg != 0.0 ? 1 : 0;
+        const double ang = r.angle_deg * (3.14159265358979323846 / 180.0);
+        A.reg[k].cr = A.reg[k].rot ? cos(ang) : 1.0;
+        A.reg[k].sr = A.reg[k].rot ? sin(ang) : 0.0;
+        const double cr = A.reg[k].cr, sr = A.reg[k].sr;
+        A.reg[k].hw[0] = sqrt(r.semi[0] * r.semi[0] * cr * cr + r.semi[1] * r.semi[1] * sr * sr);
+        A.reg[k].hw[1] = sqrt(r.semi[0] * r.semi[0] * sr * sr + r.semi[1] * r.semi[1] * cr * cr);
     }
     const int64_t nv = n_voxels(ph);
     const int64_t blocks = (nv + 255) / 256;

@@ -59,6 +59,9 @@ struct JobDev {
     double hl_k;         // Highland: 13.6 MeV / (beta c p)
     double hl_x0inv;     // Highland: 1 / X0 (1/mm)
     double hl_lnb2;      // Highland: ln(beta^2)
+    double orot[2];      // outer boundary turned by its angle: cosine, sine
+    int32_t orot_on;     // the outer boundary is turned
+    int32_t pad2_;
 };
 
 // ------------------------------------------------------------------ math helpers
@@ -164,13 +167,29 @@ template <typename R, int DIM>
 __device__ __forceinline__ bool boundary_hit(const JobDev &J, const R Q[3], const R d[3], R &l1, R &l2) {
     R a = R(0), b = R(0), c = R(-1);
     const int na = (DIM == 3 && J.outer_axes == 3) ? 3 : 2;
+    R qv[3], dv[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        qv[i] = Q[i] - R(J.oc[i]);
+        dv[i] = d[i];
+    }
+    if (J.orot_on) {
+        // into the frame of the turned ellipse (x-y rotation by minus its angle)
+        const R cr = R(J.orot[0]), sr = R(J.orot[1]);
+        const R q0 = cr * qv[0] + sr * qv[1], q1 = cr * qv[1] - sr * qv[0];
+        const R d0 = cr * dv[0] + sr * dv[1], d1 = cr * dv[1] - sr * dv[0];
+        qv[0] = q0;
+        qv[1] = q1;
+        dv[0] = d0;
+        dv[1] = d1;
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         if (i < na) {
-            const R q = Q[i] - R(J.oc[i]);
+            const R q = qv[i];
             const R w = R(J.inv_s2[i]);
-            a += d[i] * d[i] * w;
-            b += q * d[i] * w;
+            a += dv[i] * dv[i] * w;
+            b += q * dv[i] * w;
             c += q * q * w;
         }
     }

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libpct.so")
 
 PCT_OK, PCT_EINVAL, PCT_ERANGE, PCT_ECAPACITY, PCT_EWORKSPACE, PCT_EHIP, PCT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 PCT_ELLIPSE, PCT_ELLIPSOID = 0, 1
-PCT_CORNER_AVG, PCT_CENTER = 0, 1
+PCT_CORNER_AVG, PCT_CENTER, PCT_AREA_AVG = 0, 1, 2
 PCT_STRAIGHT, PCT_HERMITE = 0, 1
 PCT_F32, PCT_F16 = 0, 1
 PCT_MIXED, PCT_PLAIN_F32 = 0, 1
@@ -25,7 +25,7 @@ PCT_ORDER_GIVEN, PCT_ORDER_LPT = 0, 1
 PCT_SCATTER_FIXED, PCT_SCATTER_HIGHLAND = 0, 1
 
 SHAPES = {"ellipse": PCT_ELLIPSE, "ellipsoid": PCT_ELLIPSOID}
-VOXELIZE = {"corner_avg": PCT_CORNER_AVG, "center": PCT_CENTER}
+VOXELIZE = {"corner_avg": PCT_CORNER_AVG, "center": PCT_CENTER, "area_avg": PCT_AREA_AVG}
 PATHS = {"straight": PCT_STRAIGHT, "hermite": PCT_HERMITE}
 VAL_DTYPES = {"f32": PCT_F32, "f16": PCT_F16}
 PRECISIONS = {"mixed": PCT_MIXED, "plain_f32": PCT_PLAIN_F32}
@@ -45,13 +45,13 @@ class PctError(RuntimeError):
 
 class Region(C.Structure):
     _fields_ = [("shape", C.c_int32), ("rsp", C.c_float), ("center", C.c_double * 3),
-                ("semi", C.c_double * 3)]
+                ("semi", C.c_double * 3), ("angle_deg", C.c_double)]
 
 
 class Phantom(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double * 3),
                 ("origin", C.c_double * 3), ("n_regions", C.c_int32), ("voxelize", C.c_int32),
-                ("regions", C.POINTER(Region))]
+                ("regions", C.POINTER(Region)), ("area_samples", C.c_int32)]
 
 
 class Beam(C.Structure):
@@ -162,6 +162,7 @@ def make_phantom(ph: dict):
     for i, r in enumerate(regs):
         arr[i].shape = SHAPES[r["shape"]]
         arr[i].rsp = float(r["rsp"])
+        arr[i].angle_deg = float(r.get("angle_deg", 0.0))
         arr[i].center[:] = [float(v) for v in list(r["center"]) + [0.0] * (3 - len(r["center"]))]
         arr[i].semi[:] = [float(v) for v in list(r["semi"]) + [1.0] * (3 - len(r["semi"]))]
     p = Phantom()
@@ -179,6 +180,7 @@ def make_phantom(ph: dict):
     p.n_regions = len(regs)
     p.voxelize = VOXELIZE[ph.get("voxelize", "corner_avg")]
     p.regions = C.cast(arr, C.POINTER(Region))
+    p.area_samples = int(ph.get("area_samples") or 0)
     return p, arr
 
 

@@ -20,8 +20,9 @@ import numpy as np
 RSP_SET = (0.0, 0.9, 1.0, 1.04, 1.6)
 
 
-def _e(center, semi, rsp, shape="ellipse"):
-    return {"shape": shape, "center": list(center), "semi": list(semi), "rsp": float(rsp)}
+def _e(center, semi, rsp, shape="ellipse", angle_deg=0.0):
+    return {"shape": shape, "center": list(center), "semi": list(semi), "rsp": float(rsp),
+            "angle_deg": float(angle_deg)}
 
 
 def neo1_regions(scale_x=1.0, scale_y=1.0):
@@ -48,6 +49,18 @@ def neo2_regions():
     ]
 
 
+def neo_turned_regions(tilt=20.0, outer_deg=0.0):
+    """NEO 1 with turned inner ellipses: ventricles tilted by +-tilt degrees, the sinus
+    by tilt / 2, and the whole outer boundary (skull and brain) by outer_deg."""
+    return [
+        _e((0, 0), (90, 70), 1.6, angle_deg=outer_deg),
+        _e((0, 0), (85, 65), 1.04, angle_deg=outer_deg),
+        _e((10, 5), (12, 6), 0.9, angle_deg=tilt),
+        _e((-10, 5), (12, 6), 0.9, angle_deg=-tilt),
+        _e((0, 55), (10, 6), 0.0, angle_deg=tilt / 2),
+    ]
+
+
 def neo_ellipsoid_regions(scale=1.0, a=90.0, b=70.0, c=80.0):
     """3D NEO: the 2D layout as ellipsoids; inner z semi-axes equal their y semi-axes."""
     sx, sy, sz = scale * a / 90.0, scale * b / 70.0, scale * c / 80.0
@@ -60,11 +73,13 @@ def neo_ellipsoid_regions(scale=1.0, a=90.0, b=70.0, c=80.0):
     ]
 
 
-def phantom(dim, n, h, regions, voxelize="corner_avg", origin=None):
+def phantom(dim, n, h, regions, voxelize="corner_avg", origin=None, area_samples=8):
+    """voxelize: "corner_avg" (the paper's examples), "center" or "area_avg" (weighted-area
+    average over area_samples^dim midpoints per voxel)."""
     n = list(n) + [1] * (3 - len(n))
     h = list(h) + [1.0] * (3 - len(h))
     return {"dim": int(dim), "n": [int(v) for v in n], "h": [float(v) for v in h],
-            "origin": origin, "regions": regions, "voxelize": voxelize}
+            "origin": origin, "regions": regions, "voxelize": voxelize, "area_samples": int(area_samples)}
 
 
 def beam(seed, n_angles, dangle_deg, n_protons, t_range, v_range=(0.0, 0.0), path="straight",
@@ -143,6 +158,16 @@ def c_paper_const():
     return cfg
 
 
+def c_paper_area():
+    """The paper's example grid with the weighted-area pixel rule (8 x 8 midpoints per
+    pixel) and turned inner ellipses, outer boundary turned by 15 degrees."""
+    cfg = c_paper()
+    cfg["name"] = "paper-2d-neo1t-200x160-straight-area"
+    cfg["phantom"] = phantom(2, (200, 160), (1.0, 1.0), neo_turned_regions(20.0, 15.0), voxelize="area_avg",
+                             area_samples=8)
+    return cfg
+
+
 def c1_highland():
     """c1 with the exit-pair widths of every proton from Highland's formula (200 MeV in
     water, X0 = 360.8 mm) instead of fixed widths."""
@@ -192,7 +217,7 @@ def c3_jobs(seed=12372, n_jobs=64):
 
 def by_name(name: str):
     table = {"c0": c0, "c1": c1, "c2": c2, "c4": c4, "paper": c_paper,
-             "paper_const": c_paper_const, "c1_highland": c1_highland}
+             "paper_const": c_paper_const, "c1_highland": c1_highland, "paper_area": c_paper_area}
     return table[name]()
 
 

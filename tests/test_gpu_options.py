@@ -82,3 +82,38 @@ def test_constant_chord_curved_lane_walk(P, oracle, W):
     cfg = W.workload("const-chord-curved", ph, bm, "f32", chord_mm=2.0)
     out = _compare(P, oracle, cfg, np.arange(3000, dtype=np.int64))
     assert bool(torch.all(out["vals"] == 2.0))
+
+
+def _phantoms_f3(W):
+    out = [W.c_paper_area()["phantom"]]
+    out.append(W.phantom(2, (120, 90), (2.0, 2.0), W.neo_turned_regions(25.0, -12.0), voxelize="area_avg",
+                         area_samples=13))
+    out.append(W.phantom(2, (120, 90), (2.0, 2.0), W.neo_turned_regions(25.0, -12.0), voxelize="corner_avg"))
+    out.append(W.phantom(2, (120, 90), (2.0, 2.0), W.neo_turned_regions(25.0, 40.0), voxelize="center"))
+    regs3 = W.neo_ellipsoid_regions()
+    regs3[2]["angle_deg"] = 30.0
+    regs3[3]["angle_deg"] = -30.0
+    regs3.append(W._e((0, -40, 0), (15, 5), 1.2, "ellipse", angle_deg=60.0))   # turned cylinder
+    out.append(W.phantom(3, (50, 50, 40), (4.0, 4.0, 4.0), regs3, voxelize="area_avg", area_samples=4))
+    return out
+
+
+def test_phantom_area_rule_and_turned_regions_bit_exact(P, oracle, W):
+    for ph in _phantoms_f3(W):
+        x = P.phantom_build(ph).cpu().numpy()
+        xo = oracle.phantom_build(ph)
+        assert np.array_equal(x, xo), (ph["voxelize"], int((x != xo).sum()))
+
+
+def test_turned_outer_boundary_parity(P, oracle, W):
+    cfg = W.c_paper_area()
+    _compare(P, oracle, cfg, _sample(cfg["beam"]["n_protons"], 3000, 13))
+    ph = W.phantom(2, (90, 80), (2.2, 2.2), W.neo_turned_regions(15.0, 35.0), voxelize="area_avg")
+    bm = W.beam(808, 16, 22.5, 4000, (-99.0, 99.0), path="hermite", sigma_in=0.01, sigma_out=0.01,
+                sigma_lat=1.0, step=0.5, noise_rel=0.01)
+    _compare(P, oracle, W.workload("turned-curved", ph, bm, "f16"), np.arange(4000, dtype=np.int64))
+    ph3 = W.phantom(3, (40, 40, 32), (5.0, 5.0, 5.0), W.neo_ellipsoid_regions())
+    ph3["regions"][0]["angle_deg"] = 25.0
+    bm3 = W.beam(809, 9, 40.0, 3000, (-100.0, 100.0), (-80.0, 80.0), path="hermite", sigma_in=0.01,
+                 sigma_out=0.01, sigma_lat=1.0, step=1.0)
+    _compare(P, oracle, W.workload("turned-3d", ph3, bm3, "f32"), np.arange(3000, dtype=np.int64))
