@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-options", action="store_true",
                     help="skip the Highland-width and constant-chord variants of the path")
     ap.add_argument("--sap-only", action="store_true", help="only the SAP reconstruction leg")
+    ap.add_argument("--no-io", action="store_true", help="skip the CSR file output leg")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample size (0: auto)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (reference for HBM byte counters)")
@@ -310,6 +311,28 @@ def sap_leg(P, W, iters=20, n_strings=100, relax=0.1):
     return out
 
 
+def io_leg(P, W):
+    """pct_csr_write of the paper's example system (A, b and x) to a temporary file."""
+    import tempfile
+    import torch
+    cfg = W.c_paper()
+    o = P.simulate(cfg)
+    torch.cuda.synchronize()
+    d = tempfile.mkdtemp(prefix="pctcsr-")
+    path = os.path.join(d, "paper.pctcsr")
+    try:
+        t0 = time.perf_counter()
+        P.csr_write(path, o["row_ptr"], o["cols"], o["vals"], o["b"], o["x"])
+        dt = time.perf_counter() - t0
+        size = os.path.getsize(path)
+    finally:
+        if os.path.exists(path):
+            os.remove(path)
+        os.rmdir(d)
+    return {"workload": cfg["name"], "bytes": size, "seconds": dt, "GBps": size / dt / 1e9,
+            "target": "a new file in " + tempfile.gettempdir()}
+
+
 def options_leg(P, W, steps, warmup):
     """The path with Highland widths per proton (c1) and with the constant chord length
     of the paper's example, against their default forms."""
@@ -414,6 +437,9 @@ def main():
 
     if not args.no_sap:
         res["sap"] = sap_leg(P, W)
+
+    if not args.no_io:
+        res["csr_write"] = io_leg(P, W)
 
     if not args.no_cpu:
         target = args.cpu_rows

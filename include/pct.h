@@ -39,6 +39,7 @@ typedef int32_t pct_status;
 #define PCT_EWORKSPACE (-4)  /* workspace missing or smaller than pct_workspace_bytes   */
 #define PCT_EHIP       (-5)  /* a HIP runtime call failed                               */
 #define PCT_EINTERNAL  (-6)  /* (device) emitted entries differ from the counted ones   */
+#define PCT_EIO        (-7)  /* a file could not be opened or written                   */
 
 /* ------------------------------------------------------------------ enumerations */
 #define PCT_ELLIPSE    0   /* ellipse in the x-y plane; in 3D an elliptic cylinder along z */
@@ -284,6 +285,32 @@ pct_status pct_sap_prepare(const pct_csr *A, const pct_sap *p, void *ws_dev, siz
  * workspace. */
 pct_status pct_sap_iterate(const pct_csr *A, const pct_sap *p, float *x_dev, int32_t n_iter, void *ws_dev,
                            size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------- file output
+ * The system written to disk in a form that reads straight into CSR (Sec. II-C): one
+ * binary file, little-endian, a 128-byte header then 64-byte-aligned sections.
+ *   offset  0  char    magic[8]      "PCTCSR01"
+ *           8  int64   n_rows        m
+ *          16  int64   n_cols        n
+ *          24  int64   nnz           row_ptr[m]
+ *          32  int32   val_dtype     PCT_F32 | PCT_F16
+ *          36  int32   version       1
+ *          40  int64   off_row_ptr   m + 1 int64
+ *          48  int64   off_cols      nnz int32
+ *          56  int64   off_vals      nnz values of val_dtype
+ *          64  int64   off_b         m float32 (0: not written)
+ *          72  int64   off_x         n float32, the true solution (0: not written)
+ *          80  zero up to 128
+ * Gaps between sections are zero. */
+#define PCT_CSR_MAGIC "PCTCSR01"
+
+/* Write A (row_ptr, cols, vals), b if A->b_dev is not NULL and x if x_dev is not NULL to
+ * `path` (created or truncated).  Waits for the work already enqueued on `stream`, then
+ * streams the device arrays through two pinned host buffers of 64 MiB (allocated and
+ * freed by the call), copying the next chunk while the current one is written.  Returns
+ * when the file is complete (this call synchronises `stream`).  nnz is read from
+ * row_ptr[m] and must not exceed A->nnz. */
+pct_status pct_csr_write(const char *path, const pct_csr *A, const float *x_dev, void *stream);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpct.so")
-SOURCES = [os.path.join(CSRC, "pct.hip"), os.path.join(CSRC, "sap.hip")]
+SOURCES = [os.path.join(CSRC, "pct.hip"), os.path.join(CSRC, "sap.hip"), os.path.join(CSRC, "csr_io.hip")]
 HEADERS = [os.path.join(CSRC, "pct_device.h"), os.path.join(CSRC, "pct_wave.h"),
            os.path.join(ROOT, "include", "pct.h")]
 
@@ -38,7 +38,7 @@ def source_digest() -> str:
     identifies the kernels a stored profile was taken from."""
     import hashlib
     files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
-                   if f.endswith((".hip", ".h")) and f != "sap.hip")
+                   if f.endswith((".hip", ".h")) and f not in ("sap.hip", "csr_io.hip"))
     files += [os.path.join(ROOT, "include", "pct.h")]
     h = hashlib.sha256(" ".join(FLAGS).encode())
     for f in files:

@@ -659,6 +659,7 @@ const char *pct_status_string(pct_status s) {
         case PCT_EWORKSPACE: return "PCT_EWORKSPACE: workspace missing or too small";
         case PCT_EHIP: return "PCT_EHIP: HIP runtime error";
         case PCT_EINTERNAL: return "PCT_EINTERNAL: emitted entries differ from the count";
+        case PCT_EIO: return "PCT_EIO: a file could not be opened or written";
         default: return "unknown pct status";
     }
 }

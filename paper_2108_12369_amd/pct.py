@@ -9,12 +9,14 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpct.so")
 
 PCT_OK, PCT_EINVAL, PCT_ERANGE, PCT_ECAPACITY, PCT_EWORKSPACE, PCT_EHIP, PCT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+PCT_EIO = -7
 PCT_ELLIPSE, PCT_ELLIPSOID = 0, 1
 PCT_CORNER_AVG, PCT_CENTER, PCT_AREA_AVG = 0, 1, 2
 PCT_STRAIGHT, PCT_HERMITE = 0, 1
@@ -34,7 +36,7 @@ SCATTER = {"fixed": PCT_SCATTER_FIXED, "highland": PCT_SCATTER_HIGHLAND}
 SYMBOLS = ("pct_status_string", "pct_version", "pct_phantom_build", "pct_workspace_bytes",
            "pct_count_rows", "pct_emit_csr", "pct_wepl", "pct_device_status", "pct_set_launch_config",
            "pct_get_launch_config", "pct_autotune", "pct_graph_create", "pct_graph_launch", "pct_graph_destroy",
-           "pct_sap_workspace_bytes", "pct_sap_prepare", "pct_sap_iterate")
+           "pct_sap_workspace_bytes", "pct_sap_prepare", "pct_sap_iterate", "pct_csr_write")
 
 
 class PctError(RuntimeError):
@@ -131,6 +133,8 @@ def lib():
         L.pct_sap_iterate.argtypes = [C.POINTER(Csr), C.POINTER(SapParams), C.c_void_p, C.c_int32, C.c_void_p,
                                       C.c_size_t, C.c_void_p]
         L.pct_sap_iterate.restype = C.c_int32
+        L.pct_csr_write.argtypes = [C.c_char_p, C.POINTER(Csr), C.c_void_p, C.c_void_p]
+        L.pct_csr_write.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -425,3 +429,49 @@ class Sap:
 
     def status(self, stream=None) -> int:
         return device_status(self.ws, stream)
+
+
+# ------------------------------------------------------------------ CSR files
+
+def make_csr(row_ptr, cols, vals, b, n_cols: int) -> Csr:
+    A = Csr()
+    A.n_rows = int(row_ptr.numel()) - 1
+    A.n_cols = int(n_cols)
+    A.val_dtype = PCT_F16 if vals.dtype == torch.float16 else PCT_F32
+    A.nnz = int(cols.numel())
+    A.row_ptr_dev = _ptr(row_ptr)
+    A.cols_dev = _ptr(cols)
+    A.vals_dev = _ptr(vals)
+    A.b_dev = _ptr(b)
+    return A
+
+
+def csr_write(path: str, row_ptr, cols, vals, b=None, x=None, n_cols: int | None = None, stream=None):
+    """pct_csr_write: the system to a binary CSR file (returns when it is complete)."""
+    n = int(n_cols if n_cols is not None else x.numel())
+    A = make_csr(row_ptr, cols, vals, b, n)
+    _check(lib().pct_csr_write(os.fsencode(path), C.byref(A), _ptr(x), _stream_ptr(stream)), "pct_csr_write")
+
+
+def read_csr(path: str, mmap: bool = True) -> dict:
+    """Read a file of pct_csr_write into numpy arrays (memory-mapped by default)."""
+    hdr = np.fromfile(path, dtype=np.uint8, count=128)
+    if bytes(hdr[:8]) != b"PCTCSR01":
+        raise ValueError(f"{path}: not a PCTCSR01 file")
+    m, n, nnz = (int(v) for v in hdr[8:32].view("<i8"))
+    val_dtype, version = (int(v) for v in hdr[32:40].view("<i4"))
+    o_rp, o_c, o_v, o_b, o_x = (int(v) for v in hdr[40:80].view("<i8"))
+    vt = np.float16 if val_dtype == PCT_F16 else np.float32
+
+    def arr(off, dt, count):
+        if mmap:
+            return np.memmap(path, dtype=dt, mode="r", offset=off, shape=(count,))
+        with open(path, "rb") as f:
+            f.seek(off)
+            return np.fromfile(f, dtype=dt, count=count)
+    out = {"n_rows": m, "n_cols": n, "nnz": nnz, "val_dtype": "f16" if val_dtype == PCT_F16 else "f32",
+           "version": version, "row_ptr": arr(o_rp, "<i8", m + 1), "cols": arr(o_c, "<i4", nnz),
+           "vals": arr(o_v, vt, nnz)}
+    out["b"] = arr(o_b, "<f4", m) if o_b else None
+    out["x"] = arr(o_x, "<f4", n) if o_x else None
+    return out

@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -33,7 +34,7 @@ def test_header_functions_exported(P):
 
 
 def test_status_strings(P):
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = P.status_string(code)
         assert s.startswith("PCT_")
     assert P.lib().pct_version() >= 100
@@ -299,3 +300,50 @@ def test_sap_validation_on_host(P):
     B = P.Csr.from_buffer_copy(A)
     B.b_dev = None
     assert L.pct_sap_prepare(C.byref(B), C.byref(p), C.c_void_p(1 << 20), need, None) == -1
+
+
+def test_csr_file_reader_follows_layout(P, tmp_path):
+    """A file laid out by hand as the header documents reads back through read_csr."""
+    rng = np.random.default_rng(1)
+    m, n = 7, 11
+    counts = rng.integers(0, 5, m)
+    rp = np.concatenate([[0], np.cumsum(counts)]).astype("<i8")
+    nnz = int(rp[-1])
+    cols = rng.integers(0, n, nnz).astype("<i4")
+    vals = rng.uniform(0, 2, nnz).astype(np.float16)
+    b = rng.uniform(0, 100, m).astype("<f4")
+    al = lambda v: (v + 63) // 64 * 64
+    o_rp = 128
+    o_c = al(o_rp + 8 * (m + 1))
+    o_v = al(o_c + 4 * nnz)
+    o_b = al(o_v + 2 * nnz)
+    end = o_b + 4 * m
+    buf = bytearray(end)
+    buf[0:8] = b"PCTCSR01"
+    buf[8:32] = np.array([m, n, nnz], "<i8").tobytes()
+    buf[32:40] = np.array([1, 1], "<i4").tobytes()
+    buf[40:80] = np.array([o_rp, o_c, o_v, o_b, 0], "<i8").tobytes()
+    buf[o_rp:o_rp + 8 * (m + 1)] = rp.tobytes()
+    buf[o_c:o_c + 4 * nnz] = cols.tobytes()
+    buf[o_v:o_v + 2 * nnz] = vals.tobytes()
+    buf[o_b:o_b + 4 * m] = b.tobytes()
+    f = tmp_path / "sys.pctcsr"
+    f.write_bytes(bytes(buf))
+    for mm in (True, False):
+        r = P.read_csr(str(f), mmap=mm)
+        assert (r["n_rows"], r["n_cols"], r["nnz"], r["val_dtype"], r["version"]) == (m, n, nnz, "f16", 1)
+        assert np.array_equal(r["row_ptr"], rp) and np.array_equal(r["cols"], cols)
+        assert np.array_equal(r["vals"], vals) and np.array_equal(r["b"], b) and r["x"] is None
+    (tmp_path / "bad").write_bytes(b"NOTACSR!" + bytes(120))
+    with pytest.raises(ValueError):
+        P.read_csr(str(tmp_path / "bad"))
+
+
+def test_csr_write_validation_on_host(P):
+    A = P.Csr(n_rows=3, n_cols=4, val_dtype=0, nnz=5, row_ptr_dev=1 << 20, cols_dev=1 << 21, vals_dev=1 << 22)
+    L = P.lib()
+    assert L.pct_csr_write(None, C.byref(A), None, None) == -1
+    for field, bad in (("n_cols", 0), ("n_rows", -1), ("val_dtype", 3), ("nnz", -2), ("row_ptr_dev", None)):
+        B = P.Csr.from_buffer_copy(A)
+        setattr(B, field, bad)
+        assert L.pct_csr_write(b"/nonexistent/x", C.byref(B), None, None) == -1, field
