@@ -37,23 +37,25 @@ namespace pct {
 constexpr int WAVE = 64;
 
 // A ray inside the box, A + l D for l in [lo, hi], cut into M items at the faces of its
-// dominant axis.  Item ends 0 < m < M lie on those faces: F(m) = c0 + c1 m.
+// dominant axis.  Item ends 0 < m < M lie on those faces: F(m) = c0 + c1 m.  The ends
+// of the ray are the same line at the parameters tS (in [0, 1]) and tE (in [M-1, M]):
+// item end m is F(min(max(m, tS), tE)).  On the dominant axis F(tS) is the clipped start
+// point exactly; elsewhere the ends agree with the clipped points to rounding.
 template <typename R>
 struct RayP {
     R c0[3], c1[3];
-    R fS[3], fE[3];         // item ends 0 and M: the clipped end points
+    R tS, tE;
     int32_t M;              // items; 0 when the ray misses the box
     int32_t lo[3], hi[3];   // voxel index range between the end voxels, per axis
 };
 
-// The spline between entry and exit: N items, one per chord.  Sample m (0 < m < N) is
-// F(m) = ((c3 m + c2) m + c1) m + c0; samples 0 and N are the entry and exit points.
-// win: per axis up to two sample ranges [a, b] (a < b; unused: -1, -1) outside of which
-// the computed samples are strictly monotone in that coordinate.
+// The spline between entry and exit: N items, one per chord.  Sample m (0 <= m <= N) is
+// F(m) = ((c3 m + c2) m + c1) m + c0: c0 is the entry point, F(N) the exit point to
+// rounding.  win: per axis up to two sample ranges [a, b] (a < b; unused: -1, -1)
+// outside of which the computed samples are strictly monotone in that coordinate.
 template <typename R>
 struct SplP {
     R c0[3], c1[3], c2[3], c3[3];
-    R fS[3], fE[3];
     int32_t N;
     int32_t win[3][4];
 };
@@ -123,6 +125,7 @@ template <typename R, int DIM, int WHICH>
 __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R D[3], R lo, R hi, bool hit,
                                          RowRefD<R, DIM> w) {
     R Av[3] = {R(0), R(0), R(0)}, Dv[3] = {R(0), R(0), R(0)};
+    R Fs[3] = {R(0), R(0), R(0)}, Fe[3] = {R(0), R(0), R(0)};
     int is[3] = {0, 0, 0}, ie[3] = {0, 0, 0};
     int dom = 0;
     R best = R(-1);
@@ -133,8 +136,8 @@ __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R 
         Dv[d] = D[d] * ih;
         const R P = A[d] + lo * D[d];
         const R E = A[d] + hi * D[d];
-        RV(w, ray[WHICH].fS[d]) = (P - R(J.o[d])) * ih;
-        RV(w, ray[WHICH].fE[d]) = (E - R(J.o[d])) * ih;
+        Fs[d] = (P - R(J.o[d])) * ih;
+        Fe[d] = (E - R(J.o[d])) * ih;
         is[d] = vox_index<R>(P, J.o[d], J.invh[d], J.n[d]);
         ie[d] = vox_index<R>(E, J.o[d], J.invh[d], J.n[d]);
         const R rate = Dv[d] < R(0) ? -Dv[d] : Dv[d];
@@ -143,13 +146,8 @@ __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R 
             dom = d;
         }
     }
-#pragma unroll
-    for (int d = DIM; d < 3; ++d) {
-        RV(w, ray[WHICH].fS[d]) = R(0);
-        RV(w, ray[WHICH].fE[d]) = R(0);
-    }
     int isd = 0, ied = 0;
-    R avd = R(0), dvd = R(1);
+    R avd = R(0), dvd = R(1), fsd = R(0), fed = R(0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d)
         if (d == dom) {
@@ -157,8 +155,12 @@ __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R 
             ied = ie[d];
             avd = Av[d];
             dvd = Dv[d];
+            fsd = Fs[d];
+            fed = Fe[d];
         }
-    const int sdom = ied >= isd ? 1 : -1;
+    // the direction along the dominant axis (a ray inside one voxel of that axis moves
+    // one way too: its end parameters keep tS <= tE)
+    const int sdom = dvd >= R(0) ? 1 : -1;
     // face of item end m: isd + m (upwards) or isd + 1 - m (downwards)
     const R c0d = R(sdom > 0 ? isd : isd + 1), c1d = R(sdom);
     bool one = true;
@@ -185,6 +187,9 @@ __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R 
         RV(w, ray[WHICH].hi[d]) = hi_;
     }
     RV(w, ray[WHICH].M) = hit ? abs(ied - isd) + 1 : 0;
+    // end parameters on the dominant axis (c1 = +-1): F(t) = c0 + c1 t
+    RV(w, ray[WHICH].tS) = hit ? (fsd - c0d) * c1d : R(0);
+    RV(w, ray[WHICH].tE) = hit ? (fed - c0d) * c1d : R(0);
     return one;
 }
 
@@ -296,8 +301,8 @@ __device__ __forceinline__ void spline_windows(R c1, R c2, R c3, int N, R thr, i
 template <typename R>
 struct LaneP {
     R c0[3], c1[3], c2[3], c3[3];
-    R fS[3], fE[3];
-    R lo[3], hi[3];
+    R tS, tE;               // parameters of the piece's ends
+    int32_t lo[3], hi[3];   // voxel index range of the piece
     int32_t M;
 };
 
@@ -311,15 +316,15 @@ __device__ __forceinline__ void lane_ray(const JobDev &J, RowRefD<R, DIM> w, Lan
         p.c1[d] = RV(w, ray[WHICH].c1[d]);
         p.c2[d] = R(0);
         p.c3[d] = R(0);
-        p.fS[d] = RV(w, ray[WHICH].fS[d]);
-        p.fE[d] = RV(w, ray[WHICH].fE[d]);
         const int top = J.n[d] - 1;
         const int rlo = RV(w, ray[WHICH].lo[d]), rhi = RV(w, ray[WHICH].hi[d]);
         const int lo = rlo < 0 ? 0 : (rlo > top ? top : rlo);
         const int hi = rhi < lo ? lo : (rhi > top ? top : rhi);
-        p.lo[d] = R(lo);
-        p.hi[d] = R(hi);
+        p.lo[d] = lo;
+        p.hi[d] = hi;
     }
+    p.tS = RV(w, ray[WHICH].tS);
+    p.tE = RV(w, ray[WHICH].tE);
     p.M = RV(w, ray[WHICH].M);
 }
 
@@ -331,40 +336,32 @@ __device__ __forceinline__ void lane_spline(const JobDev &J, RowRefD<R, DIM> w, 
         p.c1[d] = RV(w, spl.c1[d]);
         p.c2[d] = RV(w, spl.c2[d]);
         p.c3[d] = RV(w, spl.c3[d]);
-        p.fS[d] = RV(w, spl.fS[d]);
-        p.fE[d] = RV(w, spl.fE[d]);
-        p.lo[d] = R(0);
-        p.hi[d] = R(J.n[d] - 1);
+        p.lo[d] = 0;
+        p.hi[d] = J.n[d] - 1;
     }
     p.M = RV(w, spl.N);
+    p.tS = R(0);
+    p.tE = R(p.M);
 }
 
 // End of item m - 1 (m = 0: the piece's start point).  mf == m.
 template <typename R, int DIM>
 __device__ __forceinline__ void piece_point(const LaneP<R> &p, int m, R mf, R F[3]) {
+    (void)m;
+    const R t = r_fmin<R>(r_fmax<R>(mf, p.tS), p.tE);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (d < DIM) {
-            const R h = r_fma<R>(r_fma<R>(r_fma<R>(p.c3[d], mf, p.c2[d]), mf, p.c1[d]), mf, p.c0[d]);
-            F[d] = (m == p.M) ? p.fE[d] : ((m == 0) ? p.fS[d] : h);
-        } else {
-            F[d] = R(0);
-        }
-    }
+    for (int d = 0; d < 3; ++d)
+        F[d] = d < DIM ? r_fma<R>(r_fma<R>(r_fma<R>(p.c3[d], t, p.c2[d]), t, p.c1[d]), t, p.c0[d]) : R(0);
 }
 
-// Same, for 0 < m: the start point is never asked for.
+// Same, for m >= 1 >= tS (or a piece with tS = tE = 0): the same point as piece_point.
 template <typename R, int DIM>
 __device__ __forceinline__ void piece_next(const LaneP<R> &p, int m, R mf, R F[3]) {
+    (void)m;
+    const R t = r_fmin<R>(mf, p.tE);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (d < DIM) {
-            const R h = r_fma<R>(r_fma<R>(r_fma<R>(p.c3[d], mf, p.c2[d]), mf, p.c1[d]), mf, p.c0[d]);
-            F[d] = (m == p.M) ? p.fE[d] : h;
-        } else {
-            F[d] = R(0);
-        }
-    }
+    for (int d = 0; d < 3; ++d)
+        F[d] = d < DIM ? r_fma<R>(r_fma<R>(r_fma<R>(p.c3[d], t, p.c2[d]), t, p.c1[d]), t, p.c0[d]) : R(0);
 }
 
 // Voxel of a point and its position in that voxel (voxel units).  The index is kept in
@@ -378,9 +375,12 @@ __device__ __forceinline__ void piece_voxel(const LaneP<R> &p, const R F[3], int
         I[d] = 0;
         fr[d] = R(0);
         if (d < DIM) {
-            const R fl = r_fmin<R>(r_fmax<R>(r_floor<R>(F[d]), p.lo[d]), p.hi[d]);
-            fr[d] = F[d] - fl;
-            I[d] = (int)fl;
+            // truncation equals the floor for F >= 0, and the range starts at 0 or above,
+            // so this is the floor clamped into [lo, hi] (a conversion that saturates
+            // keeps any F in the range)
+            const int t = (int)F[d];
+            I[d] = min(max(t, p.lo[d]), p.hi[d]);
+            fr[d] = F[d] - R(I[d]);
         }
     }
 }
@@ -603,7 +603,7 @@ __device__ __forceinline__ void item_fast(const float hf[3], const int32_t strid
         const bool go = k < tot;
         float lc = lam[k] > lp ? lam[k] : lp;
         lc = lc < 1.f ? lc : 1.f;
-        close(k, go, wk.cur, (k == 0 ? wk.pend : 0.f) + (lc - lp) * len);
+        close(k, go, wk.cur, k == 0 ? wk.pend + (lc - lp) * len : (lc - lp) * len);
         wk.cur += go ? dcol[k] : 0;
         lp = go ? lc : lp;
     }
@@ -707,8 +707,14 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int
         base = (lane - L0 - Ls) * K;
     }
     P.M = (lane < L0) ? M0 : (spl ? Ns : (lane <= last_lane ? M1 : 0));
-    const int first = base;
-    const int last = (base + K < P.M) ? base + K : P.M;   // items [first, last)
+    // items [first, last); a lane past the pieces has the empty range at 0
+    const bool has_items = base < P.M;
+    const int first = has_items ? base : 0;
+    const int last = has_items ? ((base + K < P.M) ? base + K : P.M) : 0;
+    if (!has_items) {
+        P.tS = R(0);
+        P.tE = R(0);
+    }
     const int32_t stride[3] = {1, J.n[0], J.n[0] * J.n[1]};
     const float hf[3] = {(float)J.h[0], (float)J.h[1], (float)J.h[2]};
 
@@ -716,7 +722,7 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int
     int Is[3] = {0, 0, 0};
     R Fs[3] = {R(0), R(0), R(0)}, frs[3] = {R(0), R(0), R(0)};
     int c = 0;
-    if (first < last) {
+    {
         piece_point<R, DIM>(P, first, R(first), Fs);
         piece_voxel<R, DIM>(P, Fs, Is, frs);
         bool mono = true;
@@ -752,10 +758,6 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int
     // writes the slot of its next entry, which a later store of the wave (this lane's
     // next entry, the head of the next lane with a crossing, or the row's last entry)
     // overwrites in program order
-    // every lane stores on every call, without a branch: a lane without an entry here
-    // writes the slot of its next entry, which a later store of the wave (this lane's
-    // next entry, the head of the next lane with a crossing, or the row's last entry)
-    // overwrites in program order
     auto close = [&](int k, bool ok, int32_t col, float len) {
         (void)k;
         wk.head = (ok && wk.done == 0) ? len : wk.head;
@@ -765,25 +767,28 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int
     {
         int Ip[3] = {Is[0], Is[1], Is[2]};
         R Fp[3] = {Fs[0], Fs[1], Fs[2]}, frp[3] = {frs[0], frs[1], frs[2]};
-        R mf = R(first);
+        // every lane runs K items: past its last item end it takes that end again, an
+        // empty item (the same point, bit for bit: no crossing, no length), so the loop
+        // has no branch
+#pragma unroll 2
         for (int it = 0; it < K; ++it) {
-            const int m = first + it + 1;   // item end
-            if (m <= last) {
-                mf += R(1);
-                R Fe[3], fre[3];
-                int Ie[3];
-                piece_next<R, DIM>(P, m, mf, Fe);
-                piece_voxel<R, DIM>(P, Fe, Ie, fre);
-                if (FAST) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
-                else item_general<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+            const int m = min(first + it + 1, last);   // item end
+            const R mf = R(m);
+            R Fe[3], fre[3];
+            int Ie[3];
+            piece_next<R, DIM>(P, m, mf, Fe);
+            piece_voxel<R, DIM>(P, Fe, Ie, fre);
+            if (FAST) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+            else item_general<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    Ip[d] = Ie[d];
-                    Fp[d] = Fe[d];
-                    frp[d] = fre[d];
-                }
+            for (int d = 0; d < 3; ++d) {
+                Ip[d] = Ie[d];
+                Fp[d] = Fe[d];
+                frp[d] = fre[d];
             }
         }
+        // a lane past the pieces walked a point that need not exist: nothing of it is kept
+        if (!has_items) wk.pend = 0.f;
     }
 
     // every lane must have closed exactly the crossings it counted in pass 1
@@ -875,8 +880,6 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowRefD<R,
                 const R ih = (d < DIM) ? R(J.invh[d]) : R(0);
                 const R fS = (d < DIM) ? (p.P0[d] - R(J.o[d])) * ih : R(0);
                 const R c1 = p.c1[d] * ih * iN, c2 = p.c2[d] * ih * iN2, c3 = p.c3[d] * ih * iN3;
-                RV(w, spl.fS[d]) = fS;
-                RV(w, spl.fE[d]) = (d < DIM) ? (p.P1[d] - R(J.o[d])) * ih : R(0);
                 RV(w, spl.c0[d]) = fS;
                 RV(w, spl.c1[d]) = c1;
                 RV(w, spl.c2[d]) = c2;
@@ -902,6 +905,24 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowRefD<R,
         bfac = (double)(R(1) + R(J.noise) * z1);
     }
     RV(w, bfac) = bfac;
+}
+
+// Crossings of a ray: its voxel indices are monotone over the item ends, so per axis the
+// difference of the indices at its two ends (the same points and index rule as the walk).
+template <typename R, int DIM, int WHICH>
+__device__ __forceinline__ int64_t ray_crossings(const JobDev &J, RowRefD<R, DIM> w) {
+    LaneP<R> p;
+    lane_ray<R, DIM, WHICH>(J, w, p);
+    R F0[3], F1[3], fr[3];
+    int I0[3], I1[3];
+    piece_point<R, DIM>(p, 0, R(0), F0);
+    piece_voxel<R, DIM>(p, F0, I0, fr);
+    piece_point<R, DIM>(p, p.M, R(p.M), F1);
+    piece_voxel<R, DIM>(p, F1, I1, fr);
+    int64_t c = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) c += abs(I1[d] - I0[d]);
+    return c;
 }
 
 // Crossings of the spline, axis by axis: index differences over the monotone stretches,
@@ -953,17 +974,13 @@ __device__ __forceinline__ int64_t count_row(const JobDev &J, RowRefD<R, DIM> w,
     int64_t c = 0;
     bool any = false;
     if (RV(w, ray[0].M) > 0) {
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) c += RV(w, ray[0].hi[d]) - RV(w, ray[0].lo[d]);
+        c += ray_crossings<R, DIM, 0>(J, w);
         any = true;
     }
     if (kind == 2) {
         c += spline_crossings<R, DIM>(J, w);
         any = true;
-        if (RV(w, ray[1].M) > 0) {
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) c += RV(w, ray[1].hi[d]) - RV(w, ray[1].lo[d]);
-        }
+        if (RV(w, ray[1].M) > 0) c += ray_crossings<R, DIM, 1>(J, w);
     }
     const int64_t n = any ? c + 1 : 0;
     if (n > STAGE_CAP) {

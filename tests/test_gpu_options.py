@@ -117,3 +117,17 @@ def test_turned_outer_boundary_parity(P, oracle, W):
     bm3 = W.beam(809, 9, 40.0, 3000, (-100.0, 100.0), (-80.0, 80.0), path="hermite", sigma_in=0.01,
                  sigma_out=0.01, sigma_lat=1.0, step=1.0)
     _compare(P, oracle, W.workload("turned-3d", ph3, bm3, "f32"), np.arange(3000, dtype=np.int64))
+
+
+def test_short_rays_inside_one_voxel_both_directions(P, oracle, W):
+    """Rays that cut a grid corner stay inside one voxel of their dominant axis; moving
+    down or up along it, their end points (and so the single entry's length) must hold."""
+    ph = W.phantom(2, (16, 16), (1.0, 1.0), [W._e((0, 0), (5.0, 4.0), 1.3)])
+    bm = W.beam(4711, 8, 45.0, 8 * 2000, (-11.4, 11.4))
+    cfg = W.workload("corner-rays", ph, bm, "f32")
+    out = _compare(P, oracle, cfg, np.arange(16000, dtype=np.int64))
+    rp = out["row_ptr"].cpu().numpy()
+    assert int(((rp[1:] - rp[:-1]) == 1).sum()) > 100   # many one-entry rows
+    bm2 = W.beam(4712, 8, 45.0, 8 * 2000, (-11.4, 11.4), path="hermite", sigma_in=0.05, sigma_out=0.05,
+                 sigma_lat=1.0, step=0.25)
+    _compare(P, oracle, W.workload("corner-rays-curved", ph, bm2, "f16"), np.arange(16000, dtype=np.int64))
