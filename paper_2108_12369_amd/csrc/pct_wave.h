@@ -516,40 +516,57 @@ struct RowOut {
         wepl = 0.f;
     }
     // Write the n staged entries and add their share of b.  Lanes take consecutive
-    // entries (neighbouring voxels along the path share the cache lines of x); the
-    // entries go in two halves of 512, each issuing all its gathers, interleaved with
-    // its stores, before the first one is used.
-    __device__ __forceinline__ void flush(int n, int lane) {
-        constexpr int H = (STAGE_CAP + 1) / 2;   // entries per half
-        constexpr int U = H / WAVE;              // 8 per lane
+    // entries (neighbouring voxels along the path share the cache lines of x), in groups
+    // of 256 without branches inside a group: all LDS reads, then all gathers (an entry
+    // past the row reads x[0], one cache line for all of them, and counts 0), then the
+    // stores, so that each kind of access is in flight together.
+    template <bool WB, bool HALF>
+    __device__ __forceinline__ void flush_t(int n, int lane) {
+        constexpr int G = 4;   // chunks of 64 entries per group
         n = n < STAGE_CAP + 1 ? n : STAGE_CAP + 1;
-        const int m = n < len ? n : len;
+        const int m = store ? (n < len ? n : len) : 0;   // entries stored
+        const bool cst = chord > 0.f;
         __builtin_amdgcn_wave_barrier();
-        for (int h0 = 0; h0 < n; h0 += H) {
-            float lv[U], xv[U];
+        for (int g0 = 0; g0 < n; g0 += G * WAVE) {
+            uint2 v[G];
+            float xv[G];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                lv[u] = 0.f;
-                xv[u] = 0.f;
-                if (h0 + u * WAVE < n) {
-                    const int e = h0 + u * WAVE + lane;
-                    const uint2 v = e < n ? stage[e] : make_uint2(0u, 0u);
-                    lv[u] = __uint_as_float(v.y);
-                    if (want_b) xv[u] = x[v.x < nvox ? v.x : 0u];
-                    if (store && e < m) {
-                        const float sv = chord > 0.f ? chord : lv[u];
-                        cols[e] = (int32_t)v.x;
-                        if (half) vh[e] = __half_as_ushort(__float2half_rn(sv));
-                        else vf[e] = sv;
-                    }
+            for (int u = 0; u < G; ++u) v[u] = stage[g0 + u * WAVE + lane];   // < 1024: in the slice
+            if (WB) {
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const int e = g0 + u * WAVE + lane;
+                    xv[u] = x[(e < n && v[u].x < nvox) ? v[u].x : 0u];
                 }
             }
-            if (want_b) {
 #pragma unroll
-                for (int u = 0; u < U; ++u) wepl = fmaf(lv[u], xv[u], wepl);
+            for (int u = 0; u < G; ++u) {
+                const int e = g0 + u * WAVE + lane;
+                if (e < m) {
+                    const float sv = cst ? chord : __uint_as_float(v[u].y);
+                    cols[e] = (int32_t)v[u].x;
+                    if (HALF) vh[e] = __half_as_ushort(__float2half_rn(sv));
+                    else vf[e] = sv;
+                }
+            }
+            if (WB) {
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const int e = g0 + u * WAVE + lane;
+                    wepl = fmaf(e < n ? __uint_as_float(v[u].y) : 0.f, xv[u], wepl);
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
+    }
+    __device__ __forceinline__ void flush(int n, int lane) {
+        if (want_b) {
+            if (half) flush_t<true, true>(n, lane);
+            else flush_t<true, false>(n, lane);
+        } else {
+            if (half) flush_t<false, true>(n, lane);
+            else flush_t<false, false>(n, lane);
+        }
     }
 };
 
