@@ -10,9 +10,10 @@
 //                     k_sap_average   x_{k+1}[j] = sum_t w_t y_t[j] in FP64, t in order
 //
 // A string is a chain of dependent row updates, so the parallelism is the number of
-// strings; one wavefront walks a row's entries 64 at a time.  The rows' metadata and
-// their first entries are fetched one row ahead, so that the loads of row s+1 are in
-// flight while row s gathers, reduces and updates.
+// strings; one wavefront walks a row's entries 64 at a time.  The rows' metadata is
+// loaded 64 rows at a time (one row per lane) and the first entries of the next eight
+// rows are always in flight, so that the wave waits on the latency of HBM only once per
+// several rows.
 #include "../../include/pct.h"
 #include "pct_device.h"
 #include "pct_wave.h"
@@ -142,43 +143,49 @@ __device__ __forceinline__ void y_settle() {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
-// First PF chunks of a row's entries (column -1 past its end).
+// First PF chunks of a row's entries.  The loads are unconditional (an index past the
+// row reads a valid entry of the arrays, nnz > 0) so that nothing waits for them here;
+// whether an entry belongs to the row is decided where it is used.
 template <typename VT>
 __device__ __forceinline__ void fetch_chunks(const SapArgs &a, const RowMeta &r, int lane, int32_t (&c)[PF],
                                              float (&v)[PF]) {
+    const int64_t last = a.nnz - 1;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
         const int64_t e = r.beg + k * 64 + lane;
-        c[k] = e < r.end ? a.cols[e] : -1;
-        v[k] = e < r.end ? val_at<VT>(a.vals, e) : 0.0f;
+        const int64_t ec = e < last ? e : last;
+        c[k] = a.cols[ec];
+        v[k] = val_at<VT>(a.vals, ec);
     }
 }
 
-// The relaxed projection of one row onto y, its first PF chunks already in registers.
 template <typename VT, bool LDS>
 __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const RowMeta &r, const int32_t (&cc)[PF],
                                             const float (&cv)[PF], int lane) {
     if (r.coef == 0.0f) return;
     const uint32_t n = (uint32_t)a.n;
+    bool ok[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) ok[k] = r.beg + k * 64 + lane < r.end && (uint32_t)cc[k] < n;
     // all gathers of the prefetched chunks in flight before the first use; an entry past
     // the row or with a bad column reads y[0] and counts 0
     float yv[PF];
 #pragma unroll
-    for (int k = 0; k < PF; ++k) yv[k] = y_load<LDS>(y, (uint32_t)cc[k] < n ? cc[k] : 0);
+    for (int k = 0; k < PF; ++k) yv[k] = y_load<LDS>(y, ok[k] ? cc[k] : 0);
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < PF; ++k) acc = fma((uint32_t)cc[k] < n ? (double)cv[k] : 0.0, (double)yv[k], acc);
+    for (int k = 0; k < PF; ++k) acc = fma(ok[k] ? (double)cv[k] : 0.0, (double)yv[k], acc);
     for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
         const int32_t c = a.cols[e];
-        const bool ok = (uint32_t)c < n;
-        const float yc = y_load<LDS>(y, ok ? c : 0);
-        acc = fma(ok ? (double)val_at<VT>(a.vals, e) : 0.0, (double)yc, acc);
+        const bool okc = (uint32_t)c < n;
+        const float yc = y_load<LDS>(y, okc ? c : 0);
+        acc = fma(okc ? (double)val_at<VT>(a.vals, e) : 0.0, (double)yc, acc);
     }
     const double dot = wave_sum(acc);
     const float alpha = (float)(((double)r.b - dot) * (double)r.coef);
 #pragma unroll
     for (int k = 0; k < PF; ++k)
-        if ((uint32_t)cc[k] < n) y_add<LDS>(y, cc[k], alpha * cv[k]);
+        if (ok[k]) y_add<LDS>(y, cc[k], alpha * cv[k]);
     for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
         const int32_t c = a.cols[e];
         if ((uint32_t)c < n) y_add<LDS>(y, c, alpha * val_at<VT>(a.vals, e));
@@ -187,9 +194,34 @@ __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const Ro
     if (!LDS) y_settle();
 }
 
+// Metadata of 64 consecutive string positions, one per lane.
+struct LaneMeta {
+    int64_t beg, end;
+    float b, coef;
+};
+
+__device__ __forceinline__ LaneMeta lane_meta(const SapArgs &a, int64_t base, int64_t s1, int lane) {
+    const RowMeta r = fetch_meta(a, base + lane, s1);
+    return LaneMeta{r.beg, r.end, r.b, r.coef};
+}
+
+// Position `idx` (uniform, < 64) of the lane-held metadata, as scalars.
+__device__ __forceinline__ RowMeta meta_at(const LaneMeta &m, int idx) {
+    RowMeta r;
+    const uint64_t bg = (uint64_t)m.beg, en = (uint64_t)m.end;
+    r.beg = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(bg >> 32), idx) << 32) |
+                      (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bg, idx));
+    r.end = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(en >> 32), idx) << 32) |
+                      (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)en, idx));
+    r.b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m.b), idx));
+    r.coef = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, m.coef), idx));
+    return r;
+}
+
 template <typename VT, bool LDS>
 __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, float *Y) {
     extern __shared__ float ys[];
+    constexpr int D = 8;   // rows whose first entries are in flight
     const int lane = threadIdx.x;
     const int t = blockIdx.x;
     const int n = a.n;
@@ -199,23 +231,28 @@ __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, fl
     if (!LDS) y_settle();
     __syncthreads();
 
-    // Rows alternate between two register sets, A and B, so that the loads of the next
-    // row stay in flight while a row is projected (no copy between the sets).
+    // The string's positions go in batches of 64 whose metadata the lanes hold (this
+    // batch in A, the next one in B).  Slot j of the ring holds the first PF chunks of
+    // the row at position j (mod D); a slot is refilled with the row D positions on as
+    // soon as its row is projected, so the loads of D rows are always in flight.
     const int64_t s0 = (int64_t)t * a.m / a.M, s1 = (int64_t)(t + 1) * a.m / a.M;
-    RowMeta mA = fetch_meta(a, s0, s1), mB = fetch_meta(a, s0 + 1, s1);
-    int32_t cA[PF], cB[PF];
-    float vA[PF], vB[PF];
-    fetch_chunks<VT>(a, mA, lane, cA, vA);
-    for (int64_t s = s0; s < s1; s += 2) {
-        fetch_chunks<VT>(a, mB, lane, cB, vB);          // row s + 1
-        const RowMeta mC = fetch_meta(a, s + 2, s1);
-        project_row<VT, LDS>(a, y, mA, cA, vA, lane);   // row s
-        if (s + 1 >= s1) break;
-        fetch_chunks<VT>(a, mC, lane, cA, vA);          // row s + 2
-        const RowMeta mD = fetch_meta(a, s + 3, s1);
-        project_row<VT, LDS>(a, y, mB, cB, vB, lane);   // row s + 1
-        mA = mC;
-        mB = mD;
+    LaneMeta A = lane_meta(a, s0, s1, lane), B = lane_meta(a, s0 + 64, s1, lane);
+    int32_t cq[D][PF];
+    float vq[D][PF];
+#pragma unroll
+    for (int j = 0; j < D; ++j) fetch_chunks<VT>(a, meta_at(A, j), lane, cq[j], vq[j]);
+    for (int64_t sb = s0; sb < s1; sb += 64) {
+        for (int j0 = 0; j0 < 64; j0 += D) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                project_row<VT, LDS>(a, y, meta_at(A, j0 + j), cq[j], vq[j], lane);
+                const int nx = j0 + j + D;   // the position D on, in this batch or the next
+                const RowMeta mn = nx < 64 ? meta_at(A, nx) : meta_at(B, nx - 64);
+                fetch_chunks<VT>(a, mn, lane, cq[j], vq[j]);
+            }
+        }
+        A = B;
+        B = lane_meta(a, sb + 128, s1, lane);
     }
     if (LDS) {
         __syncthreads();
