@@ -618,13 +618,55 @@ __device__ __forceinline__ void item_fast(const float hf[3], const int32_t strid
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         const bool go = k < tot;
-        float lc = lam[k] > lp ? lam[k] : lp;
-        lc = lc < 1.f ? lc : 1.f;
+        const float lc = fminf(fmaxf(lam[k], lp), 1.f);   // lam is never NaN
         close(k, go, wk.cur, k == 0 ? wk.pend + (lc - lp) * len : (lc - lp) * len);
         wk.cur += go ? dcol[k] : 0;
         lp = go ? lc : lp;
     }
     wk.pend = (tot == 0 ? wk.pend : 0.f) + (1.f - lp) * len;
+}
+
+// Item of a straight row (one ray, every item crossing each axis at most once), measured
+// in the ray's parameter t (the item runs from t_p to t_p + dt): the distance to a face
+// over the axis' rate |c1| gives the crossing's offset in t, and the length of an offset
+// is its product with Lt, the ray's length per unit of t.  The same crossings, in the
+// same order, as item_fast; no per-item square root or reciprocal.
+template <typename R, int DIM, class F>
+__device__ __forceinline__ void item_ray(const float inv_rate[3], float Lt, float dt, const int32_t stride[3],
+                                         const int Ip[3], const R frp[3], const int Ie[3], Walker &wk, F &&close) {
+    float lam[3] = {3.f, 3.f, 3.f};
+    int32_t dcol[3] = {0, 0, 0};
+    int tot = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const int di = Ie[d] - Ip[d];
+        const bool up = di > 0;
+        const float dist = (float)(frp[d] - (up ? R(1) : R(0)));   // minus the distance when up
+        lam[d] = di != 0 ? fabsf(dist) * inv_rate[d] : 3.f;
+        dcol[d] = up ? stride[d] : -stride[d];
+        tot += di != 0 ? 1 : 0;
+    }
+#define PCT_CSWAP(a, b)                                                  \
+    if (lam[b] < lam[a]) {                                               \
+        const float tl = lam[a]; lam[a] = lam[b]; lam[b] = tl;           \
+        const int32_t tc = dcol[a]; dcol[a] = dcol[b]; dcol[b] = tc;     \
+    }
+    PCT_CSWAP(0, 1)
+    if (DIM == 3) {
+        PCT_CSWAP(1, 2)
+        PCT_CSWAP(0, 1)
+    }
+#undef PCT_CSWAP
+    float lp = 0.f;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const bool go = k < tot;
+        const float lc = fminf(fmaxf(lam[k], lp), dt);   // lam is never NaN
+        close(k, go, wk.cur, k == 0 ? wk.pend + (lc - lp) * Lt : (lc - lp) * Lt);
+        wk.cur += go ? dcol[k] : 0;
+        lp = go ? lc : lp;
+    }
+    wk.pend = (tot == 0 ? wk.pend : 0.f) + (dt - lp) * Lt;
 }
 
 // Item with any number of crossings per axis (a chord longer than a voxel).  As in the
@@ -688,15 +730,17 @@ __device__ __forceinline__ int32_t col_at(const int32_t stride[3], const int I[3
 
 // Walk one row with the whole wave; n_entries = entries produced.
 // FAST: every item crosses each axis at most once (the row's `fast` flag).
-template <typename R, int DIM, typename TW, bool FAST>
+// RAY: a straight row (kind 1) with FAST: every lane takes the one ray, whose constants
+// are the same in all lanes.
+template <typename R, int DIM, typename TW, bool FAST, bool RAY = false>
 __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int kind, RowOut<TW> &out, int lane,
                                          int64_t &n_entries) {
     // item counts as the count pass writes them; the bounds only matter for a
     // description it did not write (the walk then stays finite and the count check fails)
     const int mmax = J.nmax + 1;
     const int M0 = min(max(RV(w, ray[0].M), 0), mmax);
-    const int Ns = (kind == 2) ? min(max(RV(w, spl.N), 0), (1 << 22) + 1) : 0;
-    const int M1 = (kind == 2) ? min(max(RV(w, ray[1].M), 0), mmax) : 0;
+    const int Ns = (!RAY && kind == 2) ? min(max(RV(w, spl.N), 0), (1 << 22) + 1) : 0;
+    const int M1 = (!RAY && kind == 2) ? min(max(RV(w, ray[1].M), 0), mmax) : 0;
     const int T = M0 + Ns + M1;
     n_entries = 0;
     if (T == 0) return;
@@ -712,8 +756,8 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int
     const int last_lane = L0 + Ls + L1 - 1;
     LaneP<R> P;
     int base = 0;
-    const bool spl = lane >= L0 && lane < L0 + Ls;
-    if (lane < L0) {
+    const bool spl = !RAY && lane >= L0 && lane < L0 + Ls;
+    if (RAY || lane < L0) {
         lane_ray<R, DIM, 0>(J, w, P);
         base = lane * K;
     } else if (spl) {
@@ -723,7 +767,7 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int
         lane_ray<R, DIM, 1>(J, w, P);
         base = (lane - L0 - Ls) * K;
     }
-    P.M = (lane < L0) ? M0 : (spl ? Ns : (lane <= last_lane ? M1 : 0));
+    P.M = RAY ? M0 : ((lane < L0) ? M0 : (spl ? Ns : (lane <= last_lane ? M1 : 0)));
     // items [first, last); a lane past the pieces has the empty range at 0
     const bool has_items = base < P.M;
     const int first = has_items ? base : 0;
@@ -787,16 +831,41 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int
         // every lane runs K items: past its last item end it takes that end again, an
         // empty item (the same point, bit for bit: no crossing, no length), so the loop
         // has no branch
+        // the ray's constants (straight rows): rate of every axis per unit of t and the
+        // length per unit of t
+        float inv_rate[3] = {0.f, 0.f, 0.f}, Lt = 0.f;
+        R tp = r_fmin<R>(r_fmax<R>(R(first), P.tS), P.tE);
+        if (RAY) {
+            float l2 = 0.f;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                const float r = fabsf((float)P.c1[d]);
+                inv_rate[d] = 1.f / r;
+                const float q = r * hf[d];
+                l2 = fmaf(q, q, l2);
+            }
+            Lt = sqrtf(l2);
+        }
 #pragma unroll 2
         for (int it = 0; it < K; ++it) {
             const int m = min(first + it + 1, last);   // item end
             const R mf = R(m);
             R Fe[3], fre[3];
             int Ie[3];
-            piece_next<R, DIM>(P, m, mf, Fe);
-            piece_voxel<R, DIM>(P, Fe, Ie, fre);
-            if (FAST) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
-            else item_general<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+            if (RAY) {
+                // linear item ends: F(t) = c0 + c1 t
+                const R t = r_fmin<R>(mf, P.tE);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) Fe[d] = d < DIM ? r_fma<R>(P.c1[d], t, P.c0[d]) : R(0);
+                piece_voxel<R, DIM>(P, Fe, Ie, fre);
+                item_ray<R, DIM>(inv_rate, Lt, (float)(t - tp), stride, Ip, frp, Ie, wk, close);
+                tp = t;
+            } else {
+                piece_next<R, DIM>(P, m, mf, Fe);
+                piece_voxel<R, DIM>(P, Fe, Ie, fre);
+                if (FAST) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+                else item_general<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+            }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 Ip[d] = Ie[d];
@@ -1062,8 +1131,12 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
         out.vf = gptr((float *)J.vals + pos);
         int64_t ne = 0;
         if (kind != 0) {
-            if (RV(w, fast)) wave_row<R, DIM, TW, true>(J, w, kind, out, lane, ne);
-            else wave_row<R, DIM, TW, false>(J, w, kind, out, lane, ne);
+            if (RV(w, fast)) {
+                if (kind == 1) wave_row<R, DIM, TW, true, true>(J, w, kind, out, lane, ne);
+                else wave_row<R, DIM, TW, true>(J, w, kind, out, lane, ne);
+            } else {
+                wave_row<R, DIM, TW, false>(J, w, kind, out, lane, ne);
+            }
         }
         bad |= out.bad;
         if (out.store && ne != out.len && lane == 0) set_status_dev(status, PCT_EINTERNAL);
