@@ -389,13 +389,53 @@ __global__ void __launch_bounds__(256) k_phantom(PhantomArgs A, float *__restric
         for (int d = 0; d < A.dim; ++d) p[d] = A.o[d] + ((double)idx[d] + 0.5) * A.h[d];
         val = rsp_at(A, p);
     } else {
+        // corner average.  The corners share their coordinates per axis, so for a region
+        // whose axes are not turned the scaled coordinates (p - c) / s are divided once per
+        // axis and corner side and reused: the same values, summed in the same order, as
+        // testing every corner on its own
         const int nc = 1 << A.dim;
-        double sum = 0.0;
-        for (int c = 0; c < nc; ++c) {
-            double p[3] = {0.0, 0.0, 0.0};
-            for (int d = 0; d < A.dim; ++d) p[d] = A.o[d] + (double)(idx[d] + ((c >> d) & 1)) * A.h[d];
-            sum += rsp_at(A, p);
+        double pc[3][2];
+        for (int d = 0; d < 3; ++d)
+            for (int b = 0; b < 2; ++b) pc[d][b] = d < A.dim ? A.o[d] + (double)(idx[d] + b) * A.h[d] : 0.0;
+        double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < A.n_regions; ++k) {
+            const RegionDev &g = A.reg[k];
+            const double rsp = (double)g.rsp;
+            if (!g.rot) {
+                double u[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    if (d < g.axes)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b) u[d][b] = (pc[d][b] - g.c[d]) / g.s[d];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    if (c < nc) {
+                        double q = 0.0;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            if (i < g.axes) {
+                                const double w = u[i][(c >> i) & 1];
+                                q += w * w;
+                            }
+                        }
+                        if (q <= 1.0) v[c] = rsp;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    if (c < nc) {
+                        const double p[3] = {pc[0][c & 1], pc[1][(c >> 1) & 1], pc[2][(c >> 2) & 1]};
+                        if (region_q(g, p) <= 1.0) v[c] = rsp;
+                    }
+                }
+            }
         }
+        double sum = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c < nc) sum += v[c];
         val = sum / (double)nc;
     }
     x[j] = (float)val;
