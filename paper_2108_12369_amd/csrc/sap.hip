@@ -11,8 +11,9 @@
 //
 // A string is a chain of dependent row updates, so the parallelism is the number of
 // strings; one wavefront walks a row's entries 64 at a time.  The rows' metadata is
-// loaded 64 rows at a time (one row per lane) and the first entries of the next eight
-// rows are always in flight, so that the wave waits on the latency of HBM only once per
+// loaded 64 rows at a time (one row per lane) and the first entries of the next rows
+// are always in flight (eight rows of 256 entries with the LDS iterate, four of 512 with
+// the workspace iterate), so that the wave waits on the latency of HBM only once per
 // several rows.
 #include "../../include/pct.h"
 #include "pct_device.h"
@@ -26,7 +27,11 @@ namespace pct {
 namespace {
 
 constexpr int SAP_WAVES_PREP = 4;   // waves per block of k_sap_prepare
-constexpr int PF = 4;               // chunks of 64 entries fetched one row ahead
+// Ring of rows in flight: D rows ahead, the first PF chunks of 64 entries of each.  The
+// LDS iterate takes short rows from a long ring; the workspace iterate (large grids, long
+// curved rows) takes longer rows from a shorter ring.
+template <bool LDS> struct Ring { static constexpr int D = 8, PF = 4; };
+template <> struct Ring<false> { static constexpr int D = 4, PF = 8; };
 
 struct SapLayout {
     size_t coef_off, w_off, y_off, total;
@@ -146,7 +151,7 @@ __device__ __forceinline__ void y_settle() {
 // First PF chunks of a row's entries.  The loads are unconditional (an index past the
 // row reads a valid entry of the arrays, nnz > 0) so that nothing waits for them here;
 // whether an entry belongs to the row is decided where it is used.
-template <typename VT>
+template <typename VT, int PF>
 __device__ __forceinline__ void fetch_chunks(const SapArgs &a, const RowMeta &r, int lane, int32_t (&c)[PF],
                                              float (&v)[PF]) {
     const int64_t last = a.nnz - 1;
@@ -159,7 +164,7 @@ __device__ __forceinline__ void fetch_chunks(const SapArgs &a, const RowMeta &r,
     }
 }
 
-template <typename VT, bool LDS>
+template <typename VT, bool LDS, int PF>
 __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const RowMeta &r, const int32_t (&cc)[PF],
                                             const float (&cv)[PF], int lane) {
     if (r.coef == 0.0f) return;
@@ -221,7 +226,7 @@ __device__ __forceinline__ RowMeta meta_at(const LaneMeta &m, int idx) {
 template <typename VT, bool LDS>
 __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, float *Y) {
     extern __shared__ float ys[];
-    constexpr int D = 8;   // rows whose first entries are in flight
+    constexpr int D = Ring<LDS>::D, PF = Ring<LDS>::PF;
     const int lane = threadIdx.x;
     const int t = blockIdx.x;
     const int n = a.n;
@@ -240,15 +245,15 @@ __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, fl
     int32_t cq[D][PF];
     float vq[D][PF];
 #pragma unroll
-    for (int j = 0; j < D; ++j) fetch_chunks<VT>(a, meta_at(A, j), lane, cq[j], vq[j]);
+    for (int j = 0; j < D; ++j) fetch_chunks<VT, PF>(a, meta_at(A, j), lane, cq[j], vq[j]);
     for (int64_t sb = s0; sb < s1; sb += 64) {
         for (int j0 = 0; j0 < 64; j0 += D) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                project_row<VT, LDS>(a, y, meta_at(A, j0 + j), cq[j], vq[j], lane);
+                project_row<VT, LDS, PF>(a, y, meta_at(A, j0 + j), cq[j], vq[j], lane);
                 const int nx = j0 + j + D;   // the position D on, in this batch or the next
                 const RowMeta mn = nx < 64 ? meta_at(A, nx) : meta_at(B, nx - 64);
-                fetch_chunks<VT>(a, mn, lane, cq[j], vq[j]);
+                fetch_chunks<VT, PF>(a, mn, lane, cq[j], vq[j]);
             }
         }
         A = B;
