@@ -281,8 +281,9 @@ pct_status pct_sap_prepare(const pct_csr *A, const pct_sap *p, void *ws_dev, siz
 
 /* n_iter >= 0 iterations from x_dev (n floats, read and overwritten with the result),
  * after pct_sap_prepare on the same A, parameters and workspace.  Each string is one
- * wavefront; its iterate lives in LDS when n binary32 fit a workgroup's LDS, else in the
- * workspace. */
+ * workgroup.  Its iterate lives in LDS when n binary32 fit a workgroup's LDS (one
+ * wavefront), else in the workspace (one wavefront loads the rows, one projects them).
+ * A row's entries are all applied, also where a column repeats in the row. */
 pct_status pct_sap_iterate(const pct_csr *A, const pct_sap *p, float *x_dev, int32_t n_iter, void *ws_dev,
                            size_t ws_bytes, void *stream);
 

@@ -3,18 +3,28 @@
 //
 //   pct_sap_prepare : k_sap_prepare   one wavefront per row: checks its bounds and
 //                                     columns, coefficient lambda / ||a_i||^2 (FP64 sum)
-//   pct_sap_iterate : k_sap_string    one wavefront per string: y = x_k, then the
-//                                     relaxed projection of every row of the string in
-//                                     order; y in LDS (when n floats fit) or in the
-//                                     workspace; y_t written to the workspace
+//   pct_sap_iterate : k_sap_string    one wavefront per string, y in LDS (when n floats
+//                                     fit): y = x_k, then the relaxed projection of every
+//                                     row of the string in order; y_t to the workspace
+//                     k_sap_string_ws one workgroup of two wavefronts per string, y in the
+//                                     workspace: one wave loads the rows, the other
+//                                     projects them
 //                     k_sap_average   x_{k+1}[j] = sum_t w_t y_t[j] in FP64, t in order
 //
 // A string is a chain of dependent row updates, so the parallelism is the number of
-// strings; one wavefront walks a row's entries 64 at a time.  The rows' metadata is
-// loaded 64 rows at a time (one row per lane) and the first entries of the next rows
-// are always in flight (eight rows of 256 entries with the LDS iterate, four of 512 with
-// the workspace iterate), so that the wave waits on the latency of HBM only once per
-// several rows.
+// strings; one wavefront walks a row's entries 64 at a time.
+//
+// LDS iterate: the rows' metadata is loaded 64 rows at a time (one row per lane) and the
+// first 256 entries of the next eight rows are always in flight, so the wave waits on the
+// latency of HBM only once per several rows.
+//
+// Workspace iterate: each row update ends with a wait for its writes to y, and the
+// vector-memory counter retires in issue order, so that wait would also drain any row
+// loads in flight.  The loads therefore go to a second wavefront, which keeps two rows
+// in flight and stages each row (768 entries, values as binary32) in one of two LDS
+// slots; the two waves meet at a workgroup barrier once per row.  A row whose columns
+// are distinct (the prepare pass marks the others) is written back with plain stores,
+// which stay in the XCD's L2 for the next row's gathers; global atomic adds would not.
 #include "../../include/pct.h"
 #include "pct_device.h"
 #include "pct_wave.h"
@@ -27,11 +37,13 @@ namespace pct {
 namespace {
 
 constexpr int SAP_WAVES_PREP = 4;   // waves per block of k_sap_prepare
+constexpr int SAP_HASH_BITS = 11;   // per-wave column table of k_sap_prepare: 2048 slots
+constexpr int SAP_HASH = 1 << SAP_HASH_BITS;
 // Ring of rows in flight: D rows ahead, the first PF chunks of 64 entries of each.  The
 // LDS iterate takes short rows from a long ring; the workspace iterate (large grids, long
 // curved rows) takes longer rows from a shorter ring.
 template <bool LDS> struct Ring { static constexpr int D = 8, PF = 4; };
-template <> struct Ring<false> { static constexpr int D = 4, PF = 8; };
+template <> struct Ring<false> { static constexpr int D = 2, PF = 12; };
 
 struct SapLayout {
     size_t coef_off, w_off, y_off, total;
@@ -68,6 +80,19 @@ template <> __device__ __forceinline__ float val_at<__half>(const void *v, int64
     return __half2float(((const __half *)v)[e]);
 }
 
+// A stored value as loaded (binary32, or the 16 bits of a binary16 in a 32-bit register),
+// widened only where it is used: converting, or packing two halves into one register,
+// right after the load would make the wave wait for it there.
+template <typename VT> struct RawOf { using T = float; };
+template <> struct RawOf<__half> { using T = uint32_t; };
+template <typename VT> __device__ __forceinline__ typename RawOf<VT>::T raw_at(const void *v, int64_t e);
+template <> __device__ __forceinline__ float raw_at<float>(const void *v, int64_t e) { return ((const float *)v)[e]; }
+template <> __device__ __forceinline__ uint32_t raw_at<__half>(const void *v, int64_t e) {
+    return ((const unsigned short *)v)[e];
+}
+__device__ __forceinline__ float widen(float r) { return r; }
+__device__ __forceinline__ float widen(uint32_t r) { return __half2float(__ushort_as_half((unsigned short)r)); }
+
 // Row bounds clamped into [0, nnz]: a row whose stored bounds are outside is empty here
 // (and was flagged by the prepare pass).
 __device__ __forceinline__ void row_bounds(const SapArgs &a, int64_t i, int64_t &beg, int64_t &end) {
@@ -79,14 +104,43 @@ __device__ __forceinline__ void row_bounds(const SapArgs &a, int64_t i, int64_t 
     }
 }
 
+// Enters column c of the row tagged `tag` in a wave's open-addressing table (slots hold
+// tag << 32 | column; a slot with another tag is free).  True if the row already holds c,
+// or if no free slot was found.
+__device__ __forceinline__ bool seen_before(unsigned long long *tab, uint32_t tag, int32_t c) {
+    const unsigned long long key = ((unsigned long long)tag << 32) | (uint32_t)c;
+    uint32_t h = ((uint32_t)c * 2654435761u) >> (32 - SAP_HASH_BITS);
+    for (int step = 0; step < SAP_HASH; ++step) {
+        unsigned long long cur = tab[h];
+        if ((uint32_t)(cur >> 32) != tag) {
+            const unsigned long long prev = atomicCAS(&tab[h], cur, key);
+            if (prev == cur) return false;   // claimed
+            cur = prev;                      // another lane of this row took it
+        }
+        if (cur == key) return true;
+        h = (h + 1) & (SAP_HASH - 1);
+    }
+    return true;
+}
+
+// One wavefront per row: bounds and columns checked, coefficient lambda / ||a_i||^2 in
+// binary64.  A row that holds some column more than once (a curved path can re-enter a
+// voxel), or is too long for the column table, gets its coefficient negated: the
+// workspace iterate then adds its updates atomically instead of storing them.
 template <typename VT>
 __global__ __launch_bounds__(64 * SAP_WAVES_PREP) void k_sap_prepare(SapArgs a, float relax) {
+    __shared__ unsigned long long tabs[SAP_WAVES_PREP][SAP_HASH];
     const int lane = threadIdx.x & 63;
+    unsigned long long *tab = tabs[threadIdx.x >> 6];
+    for (int j = lane; j < SAP_HASH; j += 64) tab[j] = ~0ull;   // tag 0xffffffff: never a row's
     const int64_t wid = (int64_t)blockIdx.x * SAP_WAVES_PREP + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * SAP_WAVES_PREP;
-    for (int64_t i = wid; i < a.m; i += nw) {
+    uint32_t tag = 0;
+    for (int64_t i = wid; i < a.m; i += nw, ++tag) {
         const int64_t beg = a.row_ptr[i], end = a.row_ptr[i + 1];
         bool ok = beg >= 0 && end >= beg && end <= a.nnz;
+        const bool hashable = ok && end - beg <= SAP_HASH / 2;
+        bool dup = false;
         double nrm = 0.0;
         if (ok) {
             for (int64_t e = beg + lane; e < end; e += 64) {
@@ -94,12 +148,15 @@ __global__ __launch_bounds__(64 * SAP_WAVES_PREP) void k_sap_prepare(SapArgs a, 
                 ok = ok && (uint32_t)c < (uint32_t)a.n;
                 const double v = (double)val_at<VT>(a.vals, e);
                 nrm = fma(v, v, nrm);
+                if (hashable && seen_before(tab, tag, c)) dup = true;
             }
         }
         const bool all_ok = __builtin_amdgcn_ballot_w64(!ok) == 0;
+        const bool repeats = !hashable || __builtin_amdgcn_ballot_w64(dup) != 0;
         nrm = wave_sum(nrm);
         if (lane == 0) {
-            a.coef[i] = (all_ok && nrm > 0.0) ? (float)((double)relax / nrm) : 0.0f;
+            const float cf = (all_ok && nrm > 0.0) ? (float)((double)relax / nrm) : 0.0f;
+            a.coef[i] = repeats ? -cf : cf;
             if (!all_ok) set_status_dev(a.status, PCT_EINVAL);
         }
         if (a.order && lane == 0) {
@@ -128,12 +185,18 @@ __device__ __forceinline__ RowMeta fetch_meta(const SapArgs &a, int64_t s, int64
     return r;
 }
 
-// y[c] as the string sees it: LDS, or the workspace copy read at agent scope (past the
-// non-coherent L1, so that the atomic adds of the previous row are seen).
+// y[c] as the string sees it: LDS, or the workspace copy, which only the string's own
+// workgroup reads and writes (workgroup scope).
 template <bool LDS>
 __device__ __forceinline__ float y_load(float *y, int32_t c) {
     if (LDS) return y[c];
-    return __hip_atomic_load(y + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(y + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Workspace update of a row whose columns are distinct: y[c] = y_c + alpha v, the same
+// binary32 arithmetic as the atomic add, as a store (it stays in this XCD's L2, where the
+// next gathers find it; an atomic add makes them go further).
+__device__ __forceinline__ void y_put(float *y, int32_t c, float v) {
+    __hip_atomic_store(y + c, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 template <bool LDS>
 __device__ __forceinline__ void y_add(float *y, int32_t c, float v) {
@@ -153,20 +216,20 @@ __device__ __forceinline__ void y_settle() {
 // whether an entry belongs to the row is decided where it is used.
 template <typename VT, int PF>
 __device__ __forceinline__ void fetch_chunks(const SapArgs &a, const RowMeta &r, int lane, int32_t (&c)[PF],
-                                             float (&v)[PF]) {
+                                             typename RawOf<VT>::T (&v)[PF]) {
     const int64_t last = a.nnz - 1;
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
         const int64_t e = r.beg + k * 64 + lane;
         const int64_t ec = e < last ? e : last;
         c[k] = a.cols[ec];
-        v[k] = val_at<VT>(a.vals, ec);
+        v[k] = raw_at<VT>(a.vals, ec);
     }
 }
 
 template <typename VT, bool LDS, int PF>
 __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const RowMeta &r, const int32_t (&cc)[PF],
-                                            const float (&cv)[PF], int lane) {
+                                            const typename RawOf<VT>::T (&cv)[PF], int lane) {
     if (r.coef == 0.0f) return;
     const uint32_t n = (uint32_t)a.n;
     bool ok[PF];
@@ -179,7 +242,7 @@ __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const Ro
     for (int k = 0; k < PF; ++k) yv[k] = y_load<LDS>(y, ok[k] ? cc[k] : 0);
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < PF; ++k) acc = fma(ok[k] ? (double)cv[k] : 0.0, (double)yv[k], acc);
+    for (int k = 0; k < PF; ++k) acc = fma(ok[k] ? (double)widen(cv[k]) : 0.0, (double)yv[k], acc);
     for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
         const int32_t c = a.cols[e];
         const bool okc = (uint32_t)c < n;
@@ -187,10 +250,10 @@ __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const Ro
         acc = fma(okc ? (double)val_at<VT>(a.vals, e) : 0.0, (double)yc, acc);
     }
     const double dot = wave_sum(acc);
-    const float alpha = (float)(((double)r.b - dot) * (double)r.coef);
+    const float alpha = (float)(((double)r.b - dot) * (double)fabsf(r.coef));
 #pragma unroll
     for (int k = 0; k < PF; ++k)
-        if (ok[k]) y_add<LDS>(y, cc[k], alpha * cv[k]);
+        if (ok[k]) y_add<LDS>(y, cc[k], alpha * widen(cv[k]));
     for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
         const int32_t c = a.cols[e];
         if ((uint32_t)c < n) y_add<LDS>(y, c, alpha * val_at<VT>(a.vals, e));
@@ -223,18 +286,22 @@ __device__ __forceinline__ RowMeta meta_at(const LaneMeta &m, int idx) {
     return r;
 }
 
-template <typename VT, bool LDS>
+template <typename VT>
 __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, float *Y) {
     extern __shared__ float ys[];
+    constexpr bool LDS = true;
     constexpr int D = Ring<LDS>::D, PF = Ring<LDS>::PF;
     const int lane = threadIdx.x;
     const int t = blockIdx.x;
     const int n = a.n;
     float *yg = Y + (size_t)t * (size_t)n;
-    float *y = LDS ? ys : yg;
+    float *y = ys;
     for (int j = lane; j < n; j += 64) y[j] = x[j];
-    if (!LDS) y_settle();
     __syncthreads();
+    if (a.nnz == 0) {   // every row empty: nothing to load (and no entry to clamp to)
+        for (int j = lane; j < n; j += 64) yg[j] = ys[j];
+        return;
+    }
 
     // The string's positions go in batches of 64 whose metadata the lanes hold (this
     // batch in A, the next one in B).  Slot j of the ring holds the first PF chunks of
@@ -243,9 +310,12 @@ __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, fl
     const int64_t s0 = (int64_t)t * a.m / a.M, s1 = (int64_t)(t + 1) * a.m / a.M;
     LaneMeta A = lane_meta(a, s0, s1, lane), B = lane_meta(a, s0 + 64, s1, lane);
     int32_t cq[D][PF];
-    float vq[D][PF];
+    typename RawOf<VT>::T vq[D][PF];
 #pragma unroll
-    for (int j = 0; j < D; ++j) fetch_chunks<VT, PF>(a, meta_at(A, j), lane, cq[j], vq[j]);
+    for (int j = 0; j < D; ++j) {
+        fetch_chunks<VT, PF>(a, meta_at(A, j), lane, cq[j], vq[j]);
+        __builtin_amdgcn_sched_barrier(0);   // slots filled in order
+    }
     for (int64_t sb = s0; sb < s1; sb += 64) {
         for (int j0 = 0; j0 < 64; j0 += D) {
 #pragma unroll
@@ -259,9 +329,136 @@ __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, fl
         A = B;
         B = lane_meta(a, sb + 128, s1, lane);
     }
-    if (LDS) {
-        __syncthreads();
-        for (int j = lane; j < n; j += 64) yg[j] = ys[j];
+    __syncthreads();
+    for (int j = lane; j < n; j += 64) yg[j] = ys[j];
+}
+
+// Barrier between the two waves of k_sap_string_ws: their LDS accesses before it happen
+// before those after it (lgkmcnt(0), s_barrier); global loads stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <typename VT>
+__global__ __launch_bounds__(128) void k_sap_string_ws(SapArgs a, const float *x, float *Y) {
+    constexpr int D = Ring<false>::D, PF = Ring<false>::PF, SLOT = PF * 64;
+    __shared__ int32_t sc[2][SLOT];
+    __shared__ float sv[2][SLOT];
+    __shared__ int64_t sbeg[2], send[2];
+    __shared__ float sb[2], scoef[2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int t = blockIdx.x;
+    const int n = a.n;
+    float *y = Y + (size_t)t * (size_t)n;
+    for (int j = threadIdx.x; j < n; j += 128) y[j] = x[j];
+    __syncthreads();   // (global and LDS) the copy is in L2 before the first gathers
+    if (a.nnz == 0) return;   // every row empty (both waves leave here)
+
+    const int64_t s0 = (int64_t)t * a.m / a.M, s1 = (int64_t)(t + 1) * a.m / a.M;
+    const int64_t L = s1 - s0;
+    // Step k: the loader stages position k in slot k & 1 while the projector projects
+    // position k - 1 from slot (k - 1) & 1.  Both waves take the same number of steps
+    // (L + 1 rounded up to a multiple of D) and the barrier of each; positions past the
+    // string are empty rows (coefficient 0), so no step depends on a row's contents.
+    static_assert(D % 2 == 0 && 64 % D == 0, "ring depth");
+    const int64_t steps = (L + D) / D * D;
+    if (wave == 1) {
+        // loader: ring of D rows whose first SLOT entries are in flight
+        LaneMeta A = lane_meta(a, s0, s1, lane), B = lane_meta(a, s0 + 64, s1, lane);
+        int32_t cq[D][PF];
+        typename RawOf<VT>::T vq[D][PF];
+        // the slots are filled in order (the scheduler may not interleave them), so a
+        // slot's loads are always older than those of the slots after it
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            fetch_chunks<VT, PF>(a, meta_at(A, j), lane, cq[j], vq[j]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int64_t sb0 = 0; sb0 < steps; sb0 += 64) {
+            const int jn = steps - sb0 < 64 ? (int)(steps - sb0) : 64;
+            for (int j0 = 0; j0 < jn; j0 += D) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const int slot = j & 1;   // = k & 1, as sb0 and j0 are even
+                    const RowMeta r = meta_at(A, j0 + j);
+#pragma unroll
+                    for (int q = 0; q < PF; ++q) {
+                        sc[slot][q * 64 + lane] = cq[j][q];
+                        sv[slot][q * 64 + lane] = widen(vq[j][q]);
+                    }
+                    if (lane == 0) {
+                        sbeg[slot] = r.beg;
+                        send[slot] = r.end;
+                        sb[slot] = r.b;
+                        scoef[slot] = r.coef;
+                    }
+                    const int nx = j0 + j + D;
+                    const RowMeta mn = nx < 64 ? meta_at(A, nx) : meta_at(B, nx - 64);
+                    fetch_chunks<VT, PF>(a, mn, lane, cq[j], vq[j]);
+                    lds_barrier();
+                }
+            }
+            A = B;
+            B = lane_meta(a, s0 + sb0 + 128, s1, lane);
+        }
+    } else {
+        // projector
+        const uint32_t nu = (uint32_t)n;
+        for (int64_t k = 0; k < steps; ++k) {
+            if (k > 0) {
+                const int slot = (int)((k - 1) & 1);
+                const float cf = scoef[slot];
+                if (cf != 0.0f) {
+                    const bool repeats = cf < 0.0f;   // some column twice: atomic adds
+                    const float coef = fabsf(cf);
+                    const int64_t beg = sbeg[slot], end = send[slot];
+                    int32_t cc[PF];
+                    float cv[PF], yv[PF];
+                    bool ok[PF];
+#pragma unroll
+                    for (int q = 0; q < PF; ++q) {
+                        cc[q] = sc[slot][q * 64 + lane];
+                        cv[q] = sv[slot][q * 64 + lane];
+                        ok[q] = beg + q * 64 + lane < end && (uint32_t)cc[q] < nu;
+                    }
+#pragma unroll
+                    for (int q = 0; q < PF; ++q) yv[q] = ok[q] ? y_load<false>(y, cc[q]) : 0.0f;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int q = 0; q < PF; ++q) acc = fma(ok[q] ? (double)cv[q] : 0.0, (double)yv[q], acc);
+                    for (int64_t e = beg + SLOT + lane; e < end; e += 64) {
+                        const int32_t c = a.cols[e];
+                        const bool okc = (uint32_t)c < nu;
+                        const float yc = y_load<false>(y, okc ? c : 0);
+                        acc = fma(okc ? (double)val_at<VT>(a.vals, e) : 0.0, (double)yc, acc);
+                    }
+                    const double dot = wave_sum(acc);
+                    const float alpha = (float)(((double)sb[slot] - dot) * (double)coef);
+                    if (repeats) {
+#pragma unroll
+                        for (int q = 0; q < PF; ++q)
+                            if (ok[q]) y_add<false>(y, cc[q], alpha * cv[q]);
+                        for (int64_t e = beg + SLOT + lane; e < end; e += 64) {
+                            const int32_t c = a.cols[e];
+                            if ((uint32_t)c < nu) y_add<false>(y, c, alpha * val_at<VT>(a.vals, e));
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < PF; ++q)
+                            if (ok[q]) y_put(y, cc[q], yv[q] + alpha * cv[q]);
+                        for (int64_t e = beg + SLOT + lane; e < end; e += 64) {
+                            const int32_t c = a.cols[e];
+                            if ((uint32_t)c < nu) y_put(y, c, y_load<false>(y, c) + alpha * val_at<VT>(a.vals, e));
+                        }
+                    }
+                    // the next row's gathers must see these adds
+                    y_settle();
+                }
+            }
+            lds_barrier();
+        }
     }
 }
 
@@ -333,12 +530,12 @@ template <typename VT>
 pct_status launch_strings(const SapArgs &a, const float *x, float *Y, hipStream_t s) {
     const size_t bytes = (size_t)a.n * sizeof(float);
     if (bytes <= lds_limit()) {
-        if (hipFuncSetAttribute((const void *)k_sap_string<VT, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        if (hipFuncSetAttribute((const void *)k_sap_string<VT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)bytes) != hipSuccess)
             return PCT_EHIP;
-        hipLaunchKernelGGL((k_sap_string<VT, true>), dim3((unsigned)a.M), dim3(64), bytes, s, a, x, Y);
+        hipLaunchKernelGGL((k_sap_string<VT>), dim3((unsigned)a.M), dim3(64), bytes, s, a, x, Y);
     } else {
-        hipLaunchKernelGGL((k_sap_string<VT, false>), dim3((unsigned)a.M), dim3(64), 0, s, a, x, Y);
+        hipLaunchKernelGGL((k_sap_string_ws<VT>), dim3((unsigned)a.M), dim3(128), 0, s, a, x, Y);
     }
     return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
 }

@@ -99,6 +99,79 @@ def test_sap_workspace_path_large_grid(P, oracle, W):
     _close(got, _oracle_sap(oracle, s, x0, 2, n_strings=50, relax=0.3), 1e-5)
 
 
+def test_sap_workspace_fp16_long_rows(P, oracle, W):
+    """760 x 600 pixels of 0.25 mm (the iterate lives in HBM), binary16 values, curved rows
+    longer than the 768 entries the iterate stages per row (the rest read directly), one
+    string, ragged weighted strings in a permuted order, and more strings than rows."""
+    ph = W.phantom(2, (760, 600), (0.25, 0.25), W.neo1_regions())
+    bm = W.beam(559, 12, 15.0, 1200, (-80.0, 80.0), path="hermite", sigma_in=0.01, sigma_out=0.01,
+                sigma_lat=1.0, step=0.5)
+    s = _system(oracle, W, ph, bm, "f16")
+    lens = np.diff(s["row_ptr"])
+    assert s["n"] * 4 > 160 * 1024
+    assert (lens > 768).sum() > 50, lens.max()
+    x0 = np.zeros(s["n"])
+    got, st = _gpu_sap(P, s, x0, 2, n_strings=1, relax=0.4)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, s, x0, 2, n_strings=1, relax=0.4), 1e-5)
+    rng = np.random.default_rng(4)
+    order = rng.permutation(1200)
+    w = rng.uniform(0.1, 1.0, 7)
+    w /= w.sum()
+    x1 = rng.uniform(0, 1.5, s["n"])
+    got, st = _gpu_sap(P, s, x1, 2, n_strings=7, relax=1.1, weights=list(w), order=order)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, s, x1, 2, n_strings=7, relax=1.1, weights=w, order=order), 1e-5)
+    # the first 100 rows, 130 strings: 30 strings are empty and return x_k
+    m = 100
+    sub = dict(s, row_ptr=s["row_ptr"][: m + 1].copy(), cols=s["cols"][: s["row_ptr"][m]].copy(),
+               vals=s["vals"][: s["row_ptr"][m]].copy(), b=s["b"][:m].copy())
+    got, st = _gpu_sap(P, sub, x1, 2, n_strings=130, relax=0.9)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, sub, x1, 2, n_strings=130, relax=0.9), 1e-5)
+
+
+@pytest.mark.parametrize("grid", [(64, 48, 3.0), (300, 260, 0.7)])
+def test_sap_repeated_columns(P, oracle, W, grid):
+    """Rows that hold a column twice (as a path that re-enters a voxel would): every entry
+    counts in the dot product, the norm and the update, with y in LDS (64 x 48) and in the
+    workspace (300 x 260, where such rows take atomic adds and the others plain stores)."""
+    nx, ny, h = grid
+    ph = W.phantom(2, (nx, ny), (h, h), W.neo1_regions())
+    bm = W.beam(560, 20, 9.0, 2000, (-90.0, 90.0), path="hermite", sigma_in=0.01, sigma_out=0.01,
+                sigma_lat=1.0, step=0.5)
+    s = _system(oracle, W, ph, bm)
+    rp, cols = s["row_ptr"], s["cols"].copy()
+    rows = np.nonzero(np.diff(rp) >= 3)[0][::3]
+    assert len(rows) > 100
+    cols[rp[rows + 1] - 1] = cols[rp[rows]]   # the last entry repeats the first column
+    sd = dict(s, cols=cols)
+    x0 = np.random.default_rng(5).uniform(0, 1.5, s["n"])
+    got, st = _gpu_sap(P, sd, x0, 2, n_strings=9, relax=0.7)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, sd, x0, 2, n_strings=9, relax=0.7), 1e-5)
+
+
+@pytest.mark.parametrize("n", [1000, 60000])
+def test_sap_no_entries(P, n):
+    """A system whose rows are all empty (nnz = 0, no column or value array) leaves x as it
+    is, with y in LDS (n = 1000) and in the workspace (n = 60000)."""
+    m = 10
+    dev = "cuda"
+    rp = torch.zeros(m + 1, dtype=torch.int64, device=dev)
+    cols = torch.empty(0, dtype=torch.int32, device=dev)
+    vals = torch.empty(0, dtype=torch.float32, device=dev)
+    b = torch.ones(m, dtype=torch.float32, device=dev)
+    x0 = torch.linspace(0, 2, n, dtype=torch.float32, device=dev)
+    for M in (1, 3, 40):
+        S = P.Sap(rp, cols, vals, b, n, n_strings=M, relax=0.5)
+        x = x0.clone()
+        S.iterate(x, 2)
+        torch.cuda.synchronize()
+        assert S.status() == 0
+        assert torch.equal(x, x0)
+
+
 def test_sap_order_weights_and_ragged_strings(P, oracle, W):
     ph = W.phantom(2, (64, 48), (3.0, 3.0), W.neo1_regions())
     bm = W.beam(556, 30, 6.0, 3001, (-100.0, 100.0))
