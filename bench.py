@@ -300,7 +300,7 @@ def sap_leg(P, W, iters=20, n_strings=100, relax=0.1):
         byt = nnz * (4 + vb) + m * (8 + 4 + 4) + 3 * n_strings * n * 4 + n * 4
         xt = o["x"].double()
         err = float(torch.linalg.norm(x.double() - xt) / torch.linalg.norm(xt))
-        lds = n * 4 <= 160 * 1024
+        lds = (n + 64) * 4 <= 160 * 1024
         out[name] = {"workload": cfg["name"], "rows": m, "nnz": nnz, "cols": n, "strings": n_strings,
                      "relax": relax, "iterations": k, "ms_per_iteration": ms,
                      "row_actions_per_s": m / (ms * 1e-3), "nnz_per_s": nnz / (ms * 1e-3),

@@ -217,13 +217,19 @@ __device__ __forceinline__ void y_settle() {
 template <typename VT, int PF>
 __device__ __forceinline__ void fetch_chunks(const SapArgs &a, const RowMeta &r, int lane, int32_t (&c)[PF],
                                              typename RawOf<VT>::T (&v)[PF]) {
+    // a uniform base (the row's first entry, or the last entry of the arrays for an empty
+    // row at their end) and 32-bit lane offsets clamped to the arrays' end
     const int64_t last = a.nnz - 1;
+    const int64_t base = r.beg < last ? r.beg : last;
+    const int64_t room = last - base;
+    const uint32_t lim = room < 0x7fffffff ? (uint32_t)room : 0x7fffffffu;
+    const int32_t *cb = a.cols + base;
+    const void *vb = (const char *)a.vals + base * (int64_t)sizeof(VT);
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
-        const int64_t e = r.beg + k * 64 + lane;
-        const int64_t ec = e < last ? e : last;
-        c[k] = a.cols[ec];
-        v[k] = raw_at<VT>(a.vals, ec);
+        const uint32_t o = (uint32_t)(k * 64 + lane) < lim ? (uint32_t)(k * 64 + lane) : lim;
+        c[k] = cb[o];
+        v[k] = raw_at<VT>(vb, (int64_t)o);
     }
 }
 
@@ -232,9 +238,11 @@ __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const Ro
                                             const typename RawOf<VT>::T (&cv)[PF], int lane) {
     if (r.coef == 0.0f) return;
     const uint32_t n = (uint32_t)a.n;
+    const int64_t len64 = r.end - r.beg;   // a row is shorter than 2^31 entries
+    const uint32_t len = len64 < 0x7fffffff ? (uint32_t)len64 : 0x7fffffffu;
     bool ok[PF];
 #pragma unroll
-    for (int k = 0; k < PF; ++k) ok[k] = r.beg + k * 64 + lane < r.end && (uint32_t)cc[k] < n;
+    for (int k = 0; k < PF; ++k) ok[k] = (uint32_t)(k * 64 + lane) < len && (uint32_t)cc[k] < n;
     // all gathers of the prefetched chunks in flight before the first use; an entry past
     // the row or with a bad column reads y[0] and counts 0
     float yv[PF];
@@ -242,21 +250,33 @@ __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const Ro
     for (int k = 0; k < PF; ++k) yv[k] = y_load<LDS>(y, ok[k] ? cc[k] : 0);
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < PF; ++k) acc = fma(ok[k] ? (double)widen(cv[k]) : 0.0, (double)yv[k], acc);
-    for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
-        const int32_t c = a.cols[e];
-        const bool okc = (uint32_t)c < n;
-        const float yc = y_load<LDS>(y, okc ? c : 0);
-        acc = fma(okc ? (double)val_at<VT>(a.vals, e) : 0.0, (double)yc, acc);
+    for (int k = 0; k < PF; ++k) acc = fma((double)(ok[k] ? widen(cv[k]) : 0.0f), (double)yv[k], acc);
+    const bool tail = len > (uint32_t)(PF * 64);   // uniform
+    if (tail) {
+        for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
+            const int32_t c = a.cols[e];
+            const bool okc = (uint32_t)c < n;
+            const float yc = y_load<LDS>(y, okc ? c : 0);
+            acc = fma((double)(okc ? val_at<VT>(a.vals, e) : 0.0f), (double)yc, acc);
+        }
     }
     const double dot = wave_sum(acc);
     const float alpha = (float)(((double)r.b - dot) * (double)fabsf(r.coef));
+    if (LDS) {
+        // no branch: an entry that is not the row's adds 0 to its lane's spare slot past y
 #pragma unroll
-    for (int k = 0; k < PF; ++k)
-        if (ok[k]) y_add<LDS>(y, cc[k], alpha * widen(cv[k]));
-    for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
-        const int32_t c = a.cols[e];
-        if ((uint32_t)c < n) y_add<LDS>(y, c, alpha * val_at<VT>(a.vals, e));
+        for (int k = 0; k < PF; ++k)
+            atomicAdd(y + (ok[k] ? (uint32_t)cc[k] : n + (uint32_t)lane), ok[k] ? alpha * widen(cv[k]) : 0.0f);
+    } else {
+#pragma unroll
+        for (int k = 0; k < PF; ++k)
+            if (ok[k]) y_add<LDS>(y, cc[k], alpha * widen(cv[k]));
+    }
+    if (tail) {
+        for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
+            const int32_t c = a.cols[e];
+            if ((uint32_t)c < n) y_add<LDS>(y, c, alpha * val_at<VT>(a.vals, e));
+        }
     }
     // the next row's gathers must see these adds
     if (!LDS) y_settle();
@@ -316,15 +336,20 @@ __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, fl
         fetch_chunks<VT, PF>(a, meta_at(A, j), lane, cq[j], vq[j]);
         __builtin_amdgcn_sched_barrier(0);   // slots filled in order
     }
+    static_assert(64 % D == 0, "whole ring turns per batch");
     for (int64_t sb = s0; sb < s1; sb += 64) {
-        for (int j0 = 0; j0 < 64; j0 += D) {
+        // the position D on is in this batch, except in the batch's last ring turn
+        for (int j0 = 0; j0 < 64 - D; j0 += D) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 project_row<VT, LDS, PF>(a, y, meta_at(A, j0 + j), cq[j], vq[j], lane);
-                const int nx = j0 + j + D;   // the position D on, in this batch or the next
-                const RowMeta mn = nx < 64 ? meta_at(A, nx) : meta_at(B, nx - 64);
-                fetch_chunks<VT, PF>(a, mn, lane, cq[j], vq[j]);
+                fetch_chunks<VT, PF>(a, meta_at(A, j0 + j + D), lane, cq[j], vq[j]);
             }
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            project_row<VT, LDS, PF>(a, y, meta_at(A, 64 - D + j), cq[j], vq[j], lane);
+            fetch_chunks<VT, PF>(a, meta_at(B, j), lane, cq[j], vq[j]);
         }
         A = B;
         B = lane_meta(a, sb + 128, s1, lane);
@@ -528,7 +553,8 @@ size_t lds_limit() {
 
 template <typename VT>
 pct_status launch_strings(const SapArgs &a, const float *x, float *Y, hipStream_t s) {
-    const size_t bytes = (size_t)a.n * sizeof(float);
+    // y and one spare slot per lane (the target of the adds of entries past a row)
+    const size_t bytes = ((size_t)a.n + 64) * sizeof(float);
     if (bytes <= lds_limit()) {
         if (hipFuncSetAttribute((const void *)k_sap_string<VT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)bytes) != hipSuccess)
