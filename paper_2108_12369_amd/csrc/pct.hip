@@ -133,8 +133,10 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
 }
 
 // Count pass (one lane per row): describe the row's path in the workspace and count its
-// CSR entries.  With COUNT false the counts are not stored (WEPL-only calls).
-template <typename R, bool COUNT>
+// CSR entries.  With COUNT false the counts are not stored (WEPL-only calls).  One
+// instance per grid dimension: a block whose job has the other dimension leaves at once
+// and writes nothing (the other instance's launch covers its tile).
+template <typename R, bool COUNT, int DIM>
 __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs, int n_jobs,
                                                 int32_t *__restrict__ counts, int64_t *__restrict__ tile_sums,
                                                 int32_t *__restrict__ tile_flags, char *__restrict__ rowbuf) {
@@ -142,23 +144,17 @@ __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs,
     const int64_t tile = blockIdx.x;
     const int jid = job_of_tile(jobs, n_jobs, tile);
     const JobDev &J = jobs[jid];
+    if (J.dim != DIM) return;   // block-uniform
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     int64_t cnt = 0;
     int lane_walk = 0;
     if (r < J.row_count) {
         const int64_t g = J.row_begin + r;
         // counted in both forms: the count decides which rows the per-lane walk takes
-        if (J.dim == 3) {
-            const RowRefD<R, 3> w = row_ref<R, 3>(rowbuf, J, r);
-            setup_row<R, 3>(J, g, w);
-            cnt = count_row<R, 3>(J, w, g);
-            lane_walk = (RV(w, kind) == 3) ? 1 : 0;
-        } else {
-            const RowRefD<R, 2> w = row_ref<R, 2>(rowbuf, J, r);
-            setup_row<R, 2>(J, g, w);
-            cnt = count_row<R, 2>(J, w, g);
-            lane_walk = (RV(w, kind) == 3) ? 1 : 0;
-        }
+        const RowRefD<R, DIM> w = row_ref<R, DIM>(rowbuf, J, r);
+        setup_row<R, DIM>(J, g, w);
+        cnt = count_row<R, DIM>(J, w, g);
+        lane_walk = (RV(w, kind) == 3) ? 1 : 0;
         if (COUNT) counts[J.count_off + r] = (int32_t)cnt;
     }
     // whether the per-lane emit kernel has a row in this tile
@@ -167,6 +163,23 @@ __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs,
     if (COUNT) {
         const int64_t tot = block_sum_i64(cnt, red);
         if (threadIdx.x == 0) tile_sums[tile] = tot;
+    }
+}
+
+// The count kernel's launches for a batch: one per grid dimension present.
+template <typename R, bool COUNT>
+void launch_count(bool has2, bool has3, dim3 grid, hipStream_t s, const JobDev *J, int n_jobs, int32_t *counts,
+                  int64_t *sums, int32_t *flags, char *rows) {
+    if (has2) hipLaunchKernelGGL((k_count<R, COUNT, 2>), grid, dim3(TILE), 0, s, J, n_jobs, counts, sums, flags, rows);
+    if (has3) hipLaunchKernelGGL((k_count<R, COUNT, 3>), grid, dim3(TILE), 0, s, J, n_jobs, counts, sums, flags, rows);
+}
+
+// Grid dimensions present among the jobs that have rows.
+void dims_present(int32_t n_jobs, const pct_job *jobs, bool &has2, bool &has3) {
+    has2 = has3 = false;
+    for (int j = 0; j < n_jobs; ++j) {
+        if (jobs[j].beam->row_count == 0) continue;
+        (jobs[j].phantom->dim == 3 ? has3 : has2) = true;
     }
 }
 
@@ -769,12 +782,14 @@ pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
     int32_t *counts = (int32_t *)(w + P.L.counts_off);
     const int64_t T = P.L.total_tiles;
     if (T > 0) {
+        bool has2, has3;
+        dims_present(n_jobs, jobs, has2, has3);
         if (jobs[0].precision == PCT_MIXED)
-            hipLaunchKernelGGL((k_count<double, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums,
-                               (int32_t *)(w + P.L.flags_off), w + P.L.rows_off);
+            launch_count<double, true>(has2, has3, dim3((unsigned)T), s, J, n_jobs, counts, sums,
+                                       (int32_t *)(w + P.L.flags_off), w + P.L.rows_off);
         else
-            hipLaunchKernelGGL((k_count<float, true>), dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, sums,
-                               (int32_t *)(w + P.L.flags_off), w + P.L.rows_off);
+            launch_count<float, true>(has2, has3, dim3((unsigned)T), s, J, n_jobs, counts, sums,
+                                      (int32_t *)(w + P.L.flags_off), w + P.L.rows_off);
     }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_THREADS), 0, s, J, n_jobs, T, sums, offs, nnz_total_dev);
     if (T > 0) hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, offs);
@@ -797,18 +812,15 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
     const int64_t T = P.L.total_tiles;
     if (T == 0) return PCT_OK;
     const bool mixed = jobs[0].precision == PCT_MIXED;
-    bool has2 = false, has3 = false;
-    for (int j = 0; j < n_jobs; ++j) {
-        if (jobs[j].beam->row_count == 0) continue;
-        (jobs[j].phantom->dim == 3 ? has3 : has2) = true;
-    }
+    bool has2, has3;
+    dims_present(n_jobs, jobs, has2, has3);
     const int32_t *eorder = (const int32_t *)(w + P.L.order_off);
     int32_t *flags = (int32_t *)(w + P.L.flags_off);
     void *rows = w + P.L.rows_off;
     const dim3 grid((unsigned)T), egrid((unsigned)P.total_etiles), block(TILE);
     if (mixed) {
         char *rb = (char *)rows;
-        if (!store) hipLaunchKernelGGL((k_count<double, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, flags, rb);
+        if (!store) launch_count<double, false>(has2, has3, grid, s, J, n_jobs, nullptr, nullptr, flags, rb);
         if (store) {
             if (has2) hipLaunchKernelGGL((k_emit_wave<double, true, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
             if (has3) hipLaunchKernelGGL((k_emit_wave<double, true, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
@@ -820,7 +832,7 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
         }
     } else {
         char *rb = (char *)rows;
-        if (!store) hipLaunchKernelGGL((k_count<float, false>), grid, block, 0, s, J, n_jobs, nullptr, nullptr, flags, rb);
+        if (!store) launch_count<float, false>(has2, has3, grid, s, J, n_jobs, nullptr, nullptr, flags, rb);
         if (store) {
             if (has2) hipLaunchKernelGGL((k_emit_wave<float, true, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
             if (has3) hipLaunchKernelGGL((k_emit_wave<float, true, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
