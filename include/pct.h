@@ -189,7 +189,8 @@ pct_status pct_emit_csr(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_
                         void *stream);
 
 /* WEPL only: b_dev[r] for every row, bit-identical to the b that pct_emit_csr writes,
- * without storing A (row_ptr, cols, vals are not read or written). */
+ * without storing A (row_ptr, cols, vals are not read or written).  It runs its own
+ * count pass and, like pct_count_rows, clears the device status word first. */
 pct_status pct_wepl(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_t ws_bytes,
                     void *stream);
 

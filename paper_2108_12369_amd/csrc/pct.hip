@@ -809,8 +809,10 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
     char *w = (char *)ws;
     const JobDev *J = (const JobDev *)(w + P.L.jobs_off);
     int32_t *status = &((WsHeader *)w)->status;
+    // WEPL only runs its own count pass: the status word starts afresh, as in a count call
+    if (!store) hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, (WsHeader *)w);
     const int64_t T = P.L.total_tiles;
-    if (T == 0) return PCT_OK;
+    if (T == 0) return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
     const bool mixed = jobs[0].precision == PCT_MIXED;
     bool has2, has3;
     dims_present(n_jobs, jobs, has2, has3);

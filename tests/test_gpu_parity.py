@@ -149,6 +149,25 @@ def test_wepl_matches_emit(P, W):
     assert torch.equal(out["b"], b2)
 
 
+def test_wepl_matches_emit_2d_and_3d_batch(P, W):
+    """pct_wepl on one batch of a 2D and a 3D job (both instances of the count kernel,
+    counts not stored) gives the b that the emit of each job writes."""
+    cfgs = [W.scaled(W.c1(), n_protons=360 * 16), W.scaled(W.c2(), n_protons=90 * 64)]
+    outs = [P.simulate(c) for c in cfgs]
+    js = P.JobSet()
+    bs = []
+    for c, o in zip(cfgs, outs):
+        b2 = torch.full_like(o["b"], -1.0)
+        bs.append(b2)
+        js.add(c["phantom"], c["beam"], o["x"], b=b2, val_dtype=c["val_dtype"])
+    ws = torch.empty(P.workspace_bytes(js), dtype=torch.uint8, device="cuda")
+    P.wepl(js, ws)
+    torch.cuda.synchronize()
+    assert P.device_status(ws) == P.PCT_OK
+    for o, b2 in zip(outs, bs):
+        assert torch.equal(o["b"], b2)
+
+
 def test_capacity_overflow_is_reported_without_writes(P, W):
     cfg = W.scaled(W.c0(), n_protons=90 * 8)
     x = P.phantom_build(cfg["phantom"])

@@ -99,14 +99,16 @@ def test_sap_workspace_path_large_grid(P, oracle, W):
     _close(got, _oracle_sap(oracle, s, x0, 2, n_strings=50, relax=0.3), 1e-5)
 
 
-def test_sap_workspace_fp16_long_rows(P, oracle, W):
-    """760 x 600 pixels of 0.25 mm (the iterate lives in HBM), binary16 values, curved rows
-    longer than the 768 entries the iterate stages per row (the rest read directly), one
-    string, ragged weighted strings in a permuted order, and more strings than rows."""
+@pytest.mark.parametrize("val_dtype", ["f16", "f32"])
+def test_sap_workspace_long_rows(P, oracle, W, val_dtype):
+    """760 x 600 pixels of 0.25 mm (the iterate lives in HBM), binary16 or binary32 values,
+    curved rows longer than the 768 entries the iterate stages per row (the rest read
+    directly), one string, ragged weighted strings in a permuted order, and more strings
+    than rows."""
     ph = W.phantom(2, (760, 600), (0.25, 0.25), W.neo1_regions())
     bm = W.beam(559, 12, 15.0, 1200, (-80.0, 80.0), path="hermite", sigma_in=0.01, sigma_out=0.01,
                 sigma_lat=1.0, step=0.5)
-    s = _system(oracle, W, ph, bm, "f16")
+    s = _system(oracle, W, ph, bm, val_dtype)
     lens = np.diff(s["row_ptr"])
     assert s["n"] * 4 > 160 * 1024
     assert (lens > 768).sum() > 50, lens.max()
