@@ -203,6 +203,25 @@ def test_sap_edge_cases(P, oracle, W):
     assert np.array_equal(got, x0.astype(np.float32))
 
 
+def test_sap_bad_order_entry_is_reported_and_skipped(P, oracle, W):
+    """Order entries outside [0, m) set PCT_EINVAL; their positions project nothing, as an
+    empty row in their place would (the strings keep their positions)."""
+    ph = W.phantom(2, (32, 32), (6.0, 6.0), W.neo1_regions())
+    bm = W.beam(557, 10, 36.0, 300, (-200.0, 200.0))
+    s = _system(oracle, W, ph, bm)
+    empty = np.nonzero(np.diff(s["row_ptr"]) == 0)[0]
+    assert len(empty) > 0
+    order = np.random.default_rng(6).permutation(300)
+    bad = order.copy()
+    bad[17], bad[40] = 300, -1
+    x0 = np.linspace(0, 1, s["n"])
+    got, st = _gpu_sap(P, s, x0, 2, n_strings=5, relax=0.7, order=bad)
+    assert st == P.PCT_EINVAL
+    ref = order.copy()
+    ref[17] = ref[40] = empty[0]
+    _close(got, _oracle_sap(oracle, s, x0, 2, n_strings=5, relax=0.7, order=ref), 1e-5)
+
+
 def test_sap_bad_column_is_reported_and_skipped(P, oracle, W):
     ph = W.phantom(2, (32, 32), (6.0, 6.0), W.neo1_regions())
     bm = W.beam(558, 10, 36.0, 200, (-90.0, 90.0))
