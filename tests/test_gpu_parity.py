@@ -168,6 +168,32 @@ def test_wepl_matches_emit_2d_and_3d_batch(P, W):
         assert torch.equal(o["b"], b2)
 
 
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_emit_without_b_writes_the_same_rows(P, W, name):
+    """pct_emit_csr with b_dev NULL (the copy-out without the WEPL gathers) writes the same
+    row_ptr, cols and vals, bit for bit, in 2D and in 3D."""
+    cfg = W.scaled(W.by_name(name), n_protons=(360 if name == "c1" else 90) * 32)
+    out = P.simulate(cfg)
+    n, nnz_total = cfg["beam"]["n_protons"], out["nnz"]
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    cols = torch.full((nnz_total,), -7, dtype=torch.int32, device="cuda")
+    vals = torch.zeros(nnz_total, dtype=out["vals"].dtype, device="cuda")
+    js = P.JobSet()
+    js.add(cfg["phantom"], cfg["beam"], out["x"], row_ptr=row_ptr, val_dtype=cfg["val_dtype"])
+    ws = torch.empty(P.workspace_bytes(js), dtype=torch.uint8, device="cuda")
+    nnz = torch.empty(1, dtype=torch.int64, device="cuda")
+    P.count_rows(js, ws, nnz)
+    js2 = P.JobSet()
+    js2.add(cfg["phantom"], cfg["beam"], out["x"], row_ptr=row_ptr, cols=cols, vals=vals,
+            nnz_capacity=nnz_total, val_dtype=cfg["val_dtype"])
+    P.emit_csr(js2, ws)
+    assert P.device_status(ws) == P.PCT_OK
+    assert torch.equal(row_ptr, out["row_ptr"])
+    assert torch.equal(cols, out["cols"])
+    assert torch.equal(vals.view(torch.int16) if vals.dtype == torch.float16 else vals.view(torch.int32),
+                       out["vals"].view(torch.int16) if vals.dtype == torch.float16 else out["vals"].view(torch.int32))
+
+
 def test_capacity_overflow_is_reported_without_writes(P, W):
     cfg = W.scaled(W.c0(), n_protons=90 * 8)
     x = P.phantom_build(cfg["phantom"])
