@@ -2,7 +2,8 @@
 // (see include/pct.h for the method and the arithmetic).
 //
 //   pct_sap_prepare : k_sap_prepare   one wavefront per row: checks its bounds and
-//                                     columns, coefficient lambda / ||a_i||^2 (FP64 sum)
+//                                     columns, coefficient lambda / ||a_i||^2 (FP64 sum),
+//                                     negated for a row that holds a column twice
 //   pct_sap_iterate : k_sap_string    one wavefront per string, y in LDS (when n floats
 //                                     fit): y = x_k, then the relaxed projection of every
 //                                     row of the string in order; y_t to the workspace
@@ -185,28 +186,23 @@ __device__ __forceinline__ RowMeta fetch_meta(const SapArgs &a, int64_t s, int64
     return r;
 }
 
-// y[c] as the string sees it: LDS, or the workspace copy, which only the string's own
-// workgroup reads and writes (workgroup scope).
-template <bool LDS>
-__device__ __forceinline__ float y_load(float *y, int32_t c) {
-    if (LDS) return y[c];
+// The workspace copy of y, which only the string's own workgroup reads and writes
+// (workgroup scope).
+__device__ __forceinline__ float ws_load(float *y, int32_t c) {
     return __hip_atomic_load(y + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 // Workspace update of a row whose columns are distinct: y[c] = y_c + alpha v, the same
 // binary32 arithmetic as the atomic add, as a store (it stays in this XCD's L2, where the
 // next gathers find it; an atomic add makes them go further).
-__device__ __forceinline__ void y_put(float *y, int32_t c, float v) {
+__device__ __forceinline__ void ws_put(float *y, int32_t c, float v) {
     __hip_atomic_store(y + c, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-template <bool LDS>
-__device__ __forceinline__ void y_add(float *y, int32_t c, float v) {
-    if (LDS) atomicAdd(y + c, v);   // ds_add_f32: entries of one row may share a voxel
-    else unsafeAtomicAdd(y + c, v);
-}
+// Workspace update of a row that holds some column twice.
+__device__ __forceinline__ void ws_add(float *y, int32_t c, float v) { unsafeAtomicAdd(y + c, v); }
 
-// Workspace iterate: the wave's adds (performed in L2) are complete before its next loads
-// (which read L2).  The fence keeps the compiler from moving memory accesses across.
-__device__ __forceinline__ void y_settle() {
+// Workspace iterate: the wave's writes (performed in L2) are complete before its next
+// loads (which read L2).  The fence keeps the compiler from moving memory accesses across.
+__device__ __forceinline__ void ws_settle() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
@@ -233,7 +229,9 @@ __device__ __forceinline__ void fetch_chunks(const SapArgs &a, const RowMeta &r,
     }
 }
 
-template <typename VT, bool LDS, int PF>
+// One row of a string projected onto y in LDS (the row's first PF chunks prefetched in
+// cc / cv); the adds are LDS atomics, since the entries of a row may share a voxel.
+template <typename VT, int PF>
 __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const RowMeta &r, const int32_t (&cc)[PF],
                                             const typename RawOf<VT>::T (&cv)[PF], int lane) {
     if (r.coef == 0.0f) return;
@@ -247,7 +245,7 @@ __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const Ro
     // the row or with a bad column reads y[0] and counts 0
     float yv[PF];
 #pragma unroll
-    for (int k = 0; k < PF; ++k) yv[k] = y_load<LDS>(y, ok[k] ? cc[k] : 0);
+    for (int k = 0; k < PF; ++k) yv[k] = y[ok[k] ? cc[k] : 0];
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < PF; ++k) acc = fma((double)(ok[k] ? widen(cv[k]) : 0.0f), (double)yv[k], acc);
@@ -256,30 +254,22 @@ __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const Ro
         for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
             const int32_t c = a.cols[e];
             const bool okc = (uint32_t)c < n;
-            const float yc = y_load<LDS>(y, okc ? c : 0);
+            const float yc = y[okc ? c : 0];
             acc = fma((double)(okc ? val_at<VT>(a.vals, e) : 0.0f), (double)yc, acc);
         }
     }
     const double dot = wave_sum(acc);
     const float alpha = (float)(((double)r.b - dot) * (double)fabsf(r.coef));
-    if (LDS) {
-        // no branch: an entry that is not the row's adds 0 to its lane's spare slot past y
+    // no branch: an entry that is not the row's adds 0 to its lane's spare slot past y
 #pragma unroll
-        for (int k = 0; k < PF; ++k)
-            atomicAdd(y + (ok[k] ? (uint32_t)cc[k] : n + (uint32_t)lane), ok[k] ? alpha * widen(cv[k]) : 0.0f);
-    } else {
-#pragma unroll
-        for (int k = 0; k < PF; ++k)
-            if (ok[k]) y_add<LDS>(y, cc[k], alpha * widen(cv[k]));
-    }
+    for (int k = 0; k < PF; ++k)
+        atomicAdd(y + (ok[k] ? (uint32_t)cc[k] : n + (uint32_t)lane), ok[k] ? alpha * widen(cv[k]) : 0.0f);
     if (tail) {
         for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
             const int32_t c = a.cols[e];
-            if ((uint32_t)c < n) y_add<LDS>(y, c, alpha * val_at<VT>(a.vals, e));
+            if ((uint32_t)c < n) atomicAdd(y + c, alpha * val_at<VT>(a.vals, e));
         }
     }
-    // the next row's gathers must see these adds
-    if (!LDS) y_settle();
 }
 
 // Metadata of 64 consecutive string positions, one per lane.
@@ -309,8 +299,7 @@ __device__ __forceinline__ RowMeta meta_at(const LaneMeta &m, int idx) {
 template <typename VT>
 __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, float *Y) {
     extern __shared__ float ys[];
-    constexpr bool LDS = true;
-    constexpr int D = Ring<LDS>::D, PF = Ring<LDS>::PF;
+    constexpr int D = Ring<true>::D, PF = Ring<true>::PF;
     const int lane = threadIdx.x;
     const int t = blockIdx.x;
     const int n = a.n;
@@ -342,13 +331,13 @@ __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, fl
         for (int j0 = 0; j0 < 64 - D; j0 += D) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                project_row<VT, LDS, PF>(a, y, meta_at(A, j0 + j), cq[j], vq[j], lane);
+                project_row<VT, PF>(a, y, meta_at(A, j0 + j), cq[j], vq[j], lane);
                 fetch_chunks<VT, PF>(a, meta_at(A, j0 + j + D), lane, cq[j], vq[j]);
             }
         }
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            project_row<VT, LDS, PF>(a, y, meta_at(A, 64 - D + j), cq[j], vq[j], lane);
+            project_row<VT, PF>(a, y, meta_at(A, 64 - D + j), cq[j], vq[j], lane);
             fetch_chunks<VT, PF>(a, meta_at(B, j), lane, cq[j], vq[j]);
         }
         A = B;
@@ -449,14 +438,14 @@ __global__ __launch_bounds__(128) void k_sap_string_ws(SapArgs a, const float *x
                         ok[q] = beg + q * 64 + lane < end && (uint32_t)cc[q] < nu;
                     }
 #pragma unroll
-                    for (int q = 0; q < PF; ++q) yv[q] = ok[q] ? y_load<false>(y, cc[q]) : 0.0f;
+                    for (int q = 0; q < PF; ++q) yv[q] = ok[q] ? ws_load(y, cc[q]) : 0.0f;
                     double acc = 0.0;
 #pragma unroll
                     for (int q = 0; q < PF; ++q) acc = fma(ok[q] ? (double)cv[q] : 0.0, (double)yv[q], acc);
                     for (int64_t e = beg + SLOT + lane; e < end; e += 64) {
                         const int32_t c = a.cols[e];
                         const bool okc = (uint32_t)c < nu;
-                        const float yc = y_load<false>(y, okc ? c : 0);
+                        const float yc = ws_load(y, okc ? c : 0);
                         acc = fma(okc ? (double)val_at<VT>(a.vals, e) : 0.0, (double)yc, acc);
                     }
                     const double dot = wave_sum(acc);
@@ -464,22 +453,22 @@ __global__ __launch_bounds__(128) void k_sap_string_ws(SapArgs a, const float *x
                     if (repeats) {
 #pragma unroll
                         for (int q = 0; q < PF; ++q)
-                            if (ok[q]) y_add<false>(y, cc[q], alpha * cv[q]);
+                            if (ok[q]) ws_add(y, cc[q], alpha * cv[q]);
                         for (int64_t e = beg + SLOT + lane; e < end; e += 64) {
                             const int32_t c = a.cols[e];
-                            if ((uint32_t)c < nu) y_add<false>(y, c, alpha * val_at<VT>(a.vals, e));
+                            if ((uint32_t)c < nu) ws_add(y, c, alpha * val_at<VT>(a.vals, e));
                         }
                     } else {
 #pragma unroll
                         for (int q = 0; q < PF; ++q)
-                            if (ok[q]) y_put(y, cc[q], yv[q] + alpha * cv[q]);
+                            if (ok[q]) ws_put(y, cc[q], yv[q] + alpha * cv[q]);
                         for (int64_t e = beg + SLOT + lane; e < end; e += 64) {
                             const int32_t c = a.cols[e];
-                            if ((uint32_t)c < nu) y_put(y, c, y_load<false>(y, c) + alpha * val_at<VT>(a.vals, e));
+                            if ((uint32_t)c < nu) ws_put(y, c, ws_load(y, c) + alpha * val_at<VT>(a.vals, e));
                         }
                     }
                     // the next row's gathers must see these adds
-                    y_settle();
+                    ws_settle();
                 }
             }
             lds_barrier();
