@@ -152,9 +152,8 @@ __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs,
         const int64_t g = J.row_begin + r;
         // counted in both forms: the count decides which rows the per-lane walk takes
         const RowRefD<R, DIM> w = row_ref<R, DIM>(rowbuf, J, r);
-        setup_row<R, DIM>(J, g, w);
-        cnt = count_row<R, DIM>(J, w, g);
-        lane_walk = (RV(w, kind) == 3) ? 1 : 0;
+        const RowSetup su = setup_row<R, DIM>(J, g, w);
+        cnt = count_row<R, DIM>(J, w, g, su, lane_walk);
         if (COUNT) counts[J.count_off + r] = (int32_t)cnt;
     }
     // whether the per-lane emit kernel has a row in this tile

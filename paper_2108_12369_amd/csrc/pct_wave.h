@@ -117,13 +117,23 @@ template <typename R> __device__ __forceinline__ R r_fmin(R a, R b) {
     if constexpr (std::is_same<R, float>::value) return fminf(a, b); else return fmin(a, b);
 }
 
+// One piece of a row as a lane walks it: item end m is the polynomial at
+// t = min(max(m, tS), tE), its voxel index clamped into [lo, hi] per axis.
+template <typename R>
+struct LaneP {
+    R c0[3], c1[3], c2[3], c3[3];
+    R tS, tE;               // parameters of the piece's ends
+    int32_t lo[3], hi[3];   // voxel index range of the piece
+    int32_t M;
+};
+
 // ---------------------------------------------------------------- row description
 // The part of A + l D (l in [lo, hi], already clipped to the box) as a ray piece.
 // Returns false when a minor axis moves (almost) as fast as the dominant one: an item
 // could then cross it twice through rounding.
 template <typename R, int DIM, int WHICH>
 __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R D[3], R lo, R hi, bool hit,
-                                         RowRefD<R, DIM> w) {
+                                         RowRefD<R, DIM> w, LaneP<R> &lp) {
     R Av[3] = {R(0), R(0), R(0)}, Dv[3] = {R(0), R(0), R(0)};
     R Fs[3] = {R(0), R(0), R(0)}, Fe[3] = {R(0), R(0), R(0)};
     int is[3] = {0, 0, 0}, ie[3] = {0, 0, 0};
@@ -185,11 +195,25 @@ __device__ __forceinline__ bool make_ray(const JobDev &J, const R A[3], const R 
         RV(w, ray[WHICH].c1[d]) = c1;
         RV(w, ray[WHICH].lo[d]) = lo_;
         RV(w, ray[WHICH].hi[d]) = hi_;
+        // the piece as the emit reads it back (lane_ray: the range kept inside the grid)
+        const int top = J.n[d] - 1;
+        const int clo = lo_ < 0 ? 0 : (lo_ > top ? top : lo_);
+        lp.c0[d] = c0;
+        lp.c1[d] = c1;
+        lp.c2[d] = R(0);
+        lp.c3[d] = R(0);
+        lp.lo[d] = clo;
+        lp.hi[d] = hi_ < clo ? clo : (hi_ > top ? top : hi_);
     }
-    RV(w, ray[WHICH].M) = hit ? abs(ied - isd) + 1 : 0;
+    const int32_t M = hit ? abs(ied - isd) + 1 : 0;
     // end parameters on the dominant axis (c1 = +-1): F(t) = c0 + c1 t
-    RV(w, ray[WHICH].tS) = hit ? (fsd - c0d) * c1d : R(0);
-    RV(w, ray[WHICH].tE) = hit ? (fed - c0d) * c1d : R(0);
+    const R tS = hit ? (fsd - c0d) * c1d : R(0), tE = hit ? (fed - c0d) * c1d : R(0);
+    RV(w, ray[WHICH].M) = M;
+    RV(w, ray[WHICH].tS) = tS;
+    RV(w, ray[WHICH].tE) = tE;
+    lp.M = M;
+    lp.tS = tS;
+    lp.tE = tE;
     return one;
 }
 
@@ -298,13 +322,6 @@ __device__ __forceinline__ void spline_windows(R c1, R c2, R c3, int N, R thr, i
 }
 
 // ---------------------------------------------------------------- per-lane piece
-template <typename R>
-struct LaneP {
-    R c0[3], c1[3], c2[3], c3[3];
-    R tS, tE;               // parameters of the piece's ends
-    int32_t lo[3], hi[3];   // voxel index range of the piece
-    int32_t M;
-};
 
 // The index range is kept inside the grid whatever the description holds, so that no
 // column can leave x.
@@ -383,6 +400,46 @@ __device__ __forceinline__ void piece_voxel(const LaneP<R> &p, const R F[3], int
             fr[d] = F[d] - R(I[d]);
         }
     }
+}
+
+// Voxel index along axis d of item end m of a piece: the arithmetic of piece_point and
+// piece_voxel on that axis alone.
+template <typename R>
+__device__ __forceinline__ int axis_index(const LaneP<R> &p, int d, R mf) {
+    const R t = r_fmin<R>(r_fmax<R>(mf, p.tS), p.tE);
+    const R F = r_fma<R>(r_fma<R>(r_fma<R>(p.c3[d], t, p.c2[d]), t, p.c1[d]), t, p.c0[d]);
+    return min(max((int)F, p.lo[d]), p.hi[d]);
+}
+
+// Crossings of a ray piece: its voxel indices are monotone over the item ends, so per
+// axis the difference of the indices at its two ends.
+template <typename R, int DIM>
+__device__ __forceinline__ int64_t ray_piece_crossings(const LaneP<R> &p) {
+    int64_t c = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) c += abs(axis_index<R>(p, d, R(p.M)) - axis_index<R>(p, d, R(0)));
+    return c;
+}
+
+// Crossings of the spline along axis d: index differences over the monotone stretches,
+// sample by sample inside the recorded windows.
+template <typename R>
+__device__ __forceinline__ int64_t spline_axis_crossings(const LaneP<R> &p, int d, const int32_t win[4]) {
+    int64_t c = 0;
+    int Iprev = axis_index<R>(p, d, R(0));
+    for (int k = 0; k < 2; ++k) {
+        const int a = win[2 * k], b = win[2 * k + 1];
+        if (a < 0) continue;
+        int Ia = axis_index<R>(p, d, R(a));
+        c += abs(Ia - Iprev);
+        for (int j = a + 1; j <= b; ++j) {
+            const int Ij = axis_index<R>(p, d, R(j));
+            c += abs(Ij - Ia);
+            Ia = Ij;
+        }
+        Iprev = Ia;
+    }
+    return c + abs(axis_index<R>(p, d, R(p.M)) - Iprev);
 }
 
 // Crossings of the items between item ends j0 < j1 by walking them.
@@ -925,20 +982,35 @@ __device__ __forceinline__ R spline_max_rate(R c1, R c2, R c3, int N) {
     return g;
 }
 
+// What the count pass learns while it describes a row: its kind and, for kinds 1 and 2,
+// its number of CSR entries (1 + the face crossings of its pieces, counted from the
+// pieces as they are written, with the arithmetic the emit applies to them).
+struct RowSetup {
+    int kind;
+    int64_t n;
+};
+
 template <typename R, int DIM>
-__device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowRefD<R, DIM> w) {
+__device__ __forceinline__ RowSetup setup_row(const JobDev &J, int64_t g, RowRefD<R, DIM> w) {
     PathGeom<R> p;
     if (J.path == 1) make_path<R, DIM, true>(J, g, p);
     else make_path<R, DIM, false>(J, g, p);
     const R ninf = -r_inf<R>(), pinf = r_inf<R>();
     int kind = 0, fast = 1;   // fast: every item crosses each axis at most once
+    int64_t cross = 0;        // face crossings of the pieces
+    bool any = false;         // a piece with items
     RV(w, spl.N) = 0;
     RV(w, ray[1].M) = 0;
     if (!p.curved) {
         R lo = ninf, hi = pinf;
         const bool hit = clip_box<R, DIM>(J, p.Q, p.u, lo, hi);
         kind = hit ? 1 : 0;
-        if (!make_ray<R, DIM, 0>(J, p.Q, p.u, lo, hi, hit, w)) fast = 0;
+        LaneP<R> lp;
+        if (!make_ray<R, DIM, 0>(J, p.Q, p.u, lo, hi, hit, w, lp)) fast = 0;
+        if (lp.M > 0) {
+            cross += ray_piece_crossings<R, DIM>(lp);
+            any = true;
+        }
     } else {
         // the spline lies in the convex hull of its Bezier control points
         R b1[3], b2[3];
@@ -954,11 +1026,20 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowRefD<R,
         if (in) {
             R lo = ninf, hi = R(0);
             bool hit = clip_box<R, DIM>(J, p.P0, p.d0, lo, hi);
-            if (!make_ray<R, DIM, 0>(J, p.P0, p.d0, lo, hi, hit, w)) fast = 0;
+            LaneP<R> lp;
+            if (!make_ray<R, DIM, 0>(J, p.P0, p.d0, lo, hi, hit, w, lp)) fast = 0;
+            if (lp.M > 0) cross += ray_piece_crossings<R, DIM>(lp);
             lo = R(0);
             hi = pinf;
             hit = clip_box<R, DIM>(J, p.P1, p.d1, lo, hi);
-            if (!make_ray<R, DIM, 1>(J, p.P1, p.d1, lo, hi, hit, w)) fast = 0;
+            if (!make_ray<R, DIM, 1>(J, p.P1, p.d1, lo, hi, hit, w, lp)) fast = 0;
+            if (lp.M > 0) cross += ray_piece_crossings<R, DIM>(lp);
+            any = true;   // the spline has N >= 1 items
+            // the spline as the emit reads it back (lane_spline): t in [0, N], the grid's range
+            LaneP<R> sp;
+            sp.tS = R(0);
+            sp.tE = R(p.N);
+            sp.M = p.N;
             const R iN = p.invN, iN2 = iN * iN, iN3 = iN2 * iN;
             const R thr = sizeof(R) == 8 ? R(1e-9) : R(1e-2);
 #pragma unroll
@@ -975,6 +1056,13 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowRefD<R,
                     spline_windows<R>(c1, c2, c3, p.N, thr, win);
                     // a chord moves less than one voxel along d when |F'| < 1 over [0, N]
                     if (!(spline_max_rate<R>(c1, c2, c3, p.N) < R(0.999))) fast = 0;
+                    sp.c0[d] = fS;
+                    sp.c1[d] = c1;
+                    sp.c2[d] = c2;
+                    sp.c3[d] = c3;
+                    sp.lo[d] = 0;
+                    sp.hi[d] = J.n[d] - 1;
+                    cross += spline_axis_crossings<R>(sp, d, win);
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) RV(w, spl.win[d][k]) = win[k];
@@ -991,85 +1079,26 @@ __device__ __forceinline__ void setup_row(const JobDev &J, int64_t g, RowRefD<R,
         bfac = (double)(R(1) + R(J.noise) * z1);
     }
     RV(w, bfac) = bfac;
+    return RowSetup{kind, (kind == 1 || kind == 2) && any ? cross + 1 : 0};
 }
 
-// Crossings of a ray: its voxel indices are monotone over the item ends, so per axis the
-// difference of the indices at its two ends (the same points and index rule as the walk).
-template <typename R, int DIM, int WHICH>
-__device__ __forceinline__ int64_t ray_crossings(const JobDev &J, RowRefD<R, DIM> w) {
-    LaneP<R> p;
-    lane_ray<R, DIM, WHICH>(J, w, p);
-    R F0[3], F1[3], fr[3];
-    int I0[3], I1[3];
-    piece_point<R, DIM>(p, 0, R(0), F0);
-    piece_voxel<R, DIM>(p, F0, I0, fr);
-    piece_point<R, DIM>(p, p.M, R(p.M), F1);
-    piece_voxel<R, DIM>(p, F1, I1, fr);
-    int64_t c = 0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) c += abs(I1[d] - I0[d]);
-    return c;
-}
-
-// Crossings of the spline, axis by axis: index differences over the monotone stretches,
-// sample by sample inside the recorded ranges.
+// Number of CSR entries of a row described by w (one lane): for kinds 1 and 2 the count
+// setup_row took (1 + the face crossings of its items, exactly as wave_row produces
+// them); the per-lane walk for kind 3.  A row with more entries than a wave stages
+// becomes kind 3 here (lane_walk: the row is the per-lane kernel's).
 template <typename R, int DIM>
-__device__ __forceinline__ int64_t spline_crossings(const JobDev &J, RowRefD<R, DIM> w) {
-    LaneP<R> p;
-    lane_spline<R, DIM>(J, w, p);
-    int64_t c = 0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        auto idx = [&](int j) {
-            R F[3], fr[3];
-            int I[3];
-            piece_point<R, DIM>(p, j, R(j), F);
-            piece_voxel<R, DIM>(p, F, I, fr);
-            return I[d];
-        };
-        int Iprev = idx(0);
-        for (int k = 0; k < 2; ++k) {
-            const int a = RV(w, spl.win[d][2 * k]), b = RV(w, spl.win[d][2 * k + 1]);
-            if (a < 0) continue;
-            int Ia = idx(a);
-            c += abs(Ia - Iprev);
-            for (int j = a + 1; j <= b; ++j) {
-                const int Ij = idx(j);
-                c += abs(Ij - Ia);
-                Ia = Ij;
-            }
-            Iprev = Ia;
-        }
-        c += abs(idx(p.M) - Iprev);
-    }
-    return c;
-}
-
-// Number of CSR entries of a row described by w (one lane): 1 + the face crossings of
-// its items, exactly as wave_row produces them; the per-lane walk for kind 3.  A row
-// with more entries than a wave stages becomes kind 3 here.
-template <typename R, int DIM>
-__device__ __forceinline__ int64_t count_row(const JobDev &J, RowRefD<R, DIM> w, int64_t g) {
-    const int kind = RV(w, kind);
-    if (kind == 0) return 0;
-    if (kind == 3) {
+__device__ __forceinline__ int64_t count_row(const JobDev &J, RowRefD<R, DIM> w, int64_t g, const RowSetup &su,
+                                             int &lane_walk) {
+    lane_walk = su.kind == 3 ? 1 : 0;
+    if (su.kind == 0) return 0;
+    if (su.kind == 3) {
         CountSink s;
         trace_row<R, DIM, true>(J, g, s);
         return s.n;
     }
-    int64_t c = 0;
-    bool any = false;
-    if (RV(w, ray[0].M) > 0) {
-        c += ray_crossings<R, DIM, 0>(J, w);
-        any = true;
-    }
-    if (kind == 2) {
-        c += spline_crossings<R, DIM>(J, w);
-        any = true;
-        if (RV(w, ray[1].M) > 0) c += ray_crossings<R, DIM, 1>(J, w);
-    }
-    const int64_t n = any ? c + 1 : 0;
+    const int64_t n = su.n;
     if (n > STAGE_CAP) {
+        lane_walk = 1;
         // more entries than the wave's LDS slice holds: the per-lane walk takes the row
         RV(w, kind) = 3;
         CountSink s;
