@@ -72,18 +72,18 @@ def test_c0_full(P, oracle, W):
 
 def test_c1_sampled(P, oracle, W):
     cfg = W.c1()
-    _run_compare(P, oracle, cfg, _sample(cfg["beam"]["n_protons"], 6000, 1))
+    _run_compare(P, oracle, cfg, _sample(cfg["beam"]["n_protons"], 100_000, 1))
 
 
 def test_c2_sampled(P, oracle, W):
     cfg = W.c2()
-    _run_compare(P, oracle, cfg, _sample(cfg["beam"]["n_protons"], 3000, 2))
+    _run_compare(P, oracle, cfg, _sample(cfg["beam"]["n_protons"], 100_000, 2))
 
 
 def test_c4_first_chunk_and_chunk_invariance(P, oracle, W):
     cfg = W.c4()
     chunk = cfg["chunk_rows"]
-    out0, _ = _run_compare(P, oracle, cfg, _sample(chunk, 3000, 4), row_count=chunk)
+    out0, _ = _run_compare(P, oracle, cfg, _sample(chunk, 100_000, 4), row_count=chunk)
     rows0 = np.arange(chunk - 300, chunk, dtype=np.int64)
     a = parity.gather_rows(out0["row_ptr"], out0["cols"], out0["vals"], out0["b"], rows0)
     del out0
