@@ -65,7 +65,7 @@ def _case(W, seed):
     return W.workload(f"random-{seed}", ph, bm, vt, chord_mm=chord)
 
 
-@pytest.mark.parametrize("seed", list(range(24)))
+@pytest.mark.parametrize("seed", list(range(64)))
 def test_random_case(P, oracle, W, seed):
     cfg = _case(W, 9000 + seed)
     x = P.phantom_build(cfg["phantom"]).cpu().numpy()
