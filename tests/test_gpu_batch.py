@@ -153,3 +153,47 @@ def test_autotune_sets_a_valid_config_and_keeps_outputs(P, W):
     assert P.device_status(B.ws) == P.PCT_OK
     _equal(eager, B.snapshot())
     P.set_launch_config()
+
+
+@pytest.mark.parametrize("seed", list(range(24)))
+def test_random_batch_matches_jobs_alone(P, W, seed):
+    """A batch of 2-6 random small jobs (2D and 3D, straight or curved, fixed or Highland
+    widths, any pixel rule, exact or constant chord), in a random launch configuration,
+    writes for every job what the job writes alone, bit for bit."""
+    from tests.test_gpu_random import _case
+    rng = np.random.default_rng(5300 + seed)
+    cfgs = [_case(W, int(rng.integers(0, 10**6))) for _ in range(int(rng.integers(2, 7)))]
+    for c in cfgs:
+        c["val_dtype"] = "f16"
+    rpw, order = CONFIGS[int(rng.integers(0, len(CONFIGS)))]
+    P.set_launch_config(rows_per_wave=rpw, order=order)
+    try:
+        alone = [P.simulate(c) for c in cfgs]
+        js = P.JobSet()
+        xs, rps = [], []
+        for c in cfgs:
+            xs.append(P.phantom_build(c["phantom"]))
+            rps.append(torch.empty(c["beam"]["n_protons"] + 1, dtype=torch.int64, device="cuda"))
+            js.add(c["phantom"], c["beam"], xs[-1], row_ptr=rps[-1], val_dtype="f16")
+        ws = torch.empty(P.workspace_bytes(js), dtype=torch.uint8, device="cuda")
+        nnz = torch.empty(len(cfgs), dtype=torch.int64, device="cuda")
+        P.count_rows(js, ws, nnz)
+        js2 = P.JobSet()
+        outs = []
+        for c, x, rp, nz in zip(cfgs, xs, rps, nnz.cpu().numpy()):
+            cols = torch.empty(max(int(nz), 1), dtype=torch.int32, device="cuda")
+            vals = torch.empty(max(int(nz), 1), dtype=torch.float16, device="cuda")
+            b = torch.empty(max(c["beam"]["n_protons"], 1), dtype=torch.float32, device="cuda")
+            outs.append((cols, vals, b))
+            js2.add(c["phantom"], c["beam"], x, row_ptr=rp, cols=cols, vals=vals, b=b, nnz_capacity=int(nz),
+                    val_dtype="f16", chord_mm=c.get("chord_mm") or 0.0)
+        P.emit_csr(js2, ws)
+        assert P.device_status(ws) == P.PCT_OK
+        for a, rp, (cols, vals, b), c in zip(alone, rps, outs, cfgs):
+            n = c["beam"]["n_protons"]
+            assert torch.equal(a["row_ptr"], rp)
+            assert torch.equal(a["cols"], cols[: a["nnz"]])
+            assert torch.equal(a["vals"].view(torch.int16), vals[: a["nnz"]].view(torch.int16))
+            assert torch.equal(a["b"], b[:n])
+    finally:
+        P.set_launch_config()
