@@ -732,7 +732,9 @@ int32_t or_sizeof_beam(void) { return (int32_t)sizeof(or_beam); }
  * the next iterate is the weighted sum x_{k+1} = sum_t w_t y_t.  The update uses the
  * current y, with the residual b_i - <a_i, y> (the standard Kaczmarz sign; the printed
  * update has the other sign and x_k in place of y).  Everything in binary64.
- * weights == NULL: w_t = 1/M.  order == NULL: rows in their natural order. */
+ * weights == NULL: w_t = 1/M.  order == NULL: rows in their natural order.  A row is
+ * taken as stored: entries that share a column each count in the dot product, the norm
+ * (sum of v^2) and the update. */
 void or_sap(int64_t m, int32_t n, const int64_t *row_ptr, const int32_t *cols, const double *vals,
             const double *b, int32_t M, double lambda, const double *weights, const int64_t *order,
             double *x, int32_t n_iter)
