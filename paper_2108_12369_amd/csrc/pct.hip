@@ -935,26 +935,38 @@ pct_status pct_graph_create(int32_t n_jobs, const pct_job *jobs, int32_t build_x
         for (int j = 0; j < n_jobs; ++j)
             if (!jobs[j].x_dev) return PCT_EINVAL;
     }
-    hipStream_t s = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PCT_EHIP;
-    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        (void)hipStreamDestroy(s);
-        return PCT_EHIP;
-    }
-    if (build_x) {
+    // The count pass does not read x, so the phantom builds form a branch of their own
+    // (stream s2, forked from and joined back into the capture stream s) that runs beside
+    // the count pass; the emit, which gathers x, waits for both.
+    hipStream_t s = nullptr, s2 = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&join, hipEventDisableTiming) == hipSuccess;
+    bool capturing = ok && hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (!capturing) st = PCT_EHIP;
+    if (st == PCT_OK && build_x) {
+        if (hipEventRecord(fork, s) != hipSuccess || hipStreamWaitEvent(s2, fork, 0) != hipSuccess) st = PCT_EHIP;
         std::vector<const float *> done;
         for (int j = 0; j < n_jobs && st == PCT_OK; ++j) {
             const float *x = jobs[j].x_dev;
             if (std::find(done.begin(), done.end(), x) != done.end()) continue;
             done.push_back(x);
-            st = pct_phantom_build(jobs[j].phantom, const_cast<float *>(x), s);
+            st = pct_phantom_build(jobs[j].phantom, const_cast<float *>(x), s2);
         }
     }
     if (st == PCT_OK) st = pct_count_rows(n_jobs, jobs, ws, ws_bytes, nnz_total_dev, s);
+    if (st == PCT_OK && build_x) {
+        if (hipEventRecord(join, s2) != hipSuccess || hipStreamWaitEvent(s, join, 0) != hipSuccess) st = PCT_EHIP;
+    }
     if (st == PCT_OK) st = pct_emit_csr(n_jobs, jobs, ws, ws_bytes, s);
     hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(s, &g);
-    (void)hipStreamDestroy(s);
+    const hipError_t ec = capturing ? hipStreamEndCapture(s, &g) : hipSuccess;
+    if (join) (void)hipEventDestroy(join);
+    if (fork) (void)hipEventDestroy(fork);
+    if (s2) (void)hipStreamDestroy(s2);
+    if (s) (void)hipStreamDestroy(s);
     if (st == PCT_OK && ec != hipSuccess) st = PCT_EHIP;
     if (st != PCT_OK) {
         if (g) (void)hipGraphDestroy(g);
