@@ -16,8 +16,10 @@
 // strings; one wavefront walks a row's entries 64 at a time.
 //
 // LDS iterate: the rows' metadata is loaded 64 rows at a time (one row per lane) and the
-// first 256 entries of the next eight rows are always in flight, so the wave waits on the
-// latency of HBM only once per several rows.
+// first 384 entries of the next eight rows are always in flight, so the wave waits on the
+// latency of HBM only once per several rows.  With one wave on its SIMD, every issued
+// instruction costs the wave its full issue slot, so a row is projected with only as many
+// chunks of 64 entries as it spans (2, 4 or 6; a uniform branch on its length).
 //
 // Workspace iterate: each row update ends with a wait for its writes to y, and the
 // vector-memory counter retires in issue order, so that wait would also drain any row
@@ -43,8 +45,11 @@ constexpr int SAP_HASH = 1 << SAP_HASH_BITS;
 // Ring of rows in flight: D rows ahead, the first PF chunks of 64 entries of each.  The
 // LDS iterate takes short rows from a long ring; the workspace iterate (large grids, long
 // curved rows) takes longer rows from a shorter ring.
-template <bool LDS> struct Ring { static constexpr int D = 8, PF = 4; };
+template <bool LDS> struct Ring { static constexpr int D = 8, PF = 6; };
 template <> struct Ring<false> { static constexpr int D = 2, PF = 12; };
+// Chunk counts of the LDS iterate's shorter row bodies (a row of at most 64 * T1 entries
+// takes T1 chunks, else one of at most 64 * T2 takes T2, else PF).
+constexpr int SAP_T1 = 2, SAP_T2 = 4;
 
 struct SapLayout {
     size_t coef_off, w_off, y_off, total;
@@ -229,27 +234,26 @@ __device__ __forceinline__ void fetch_chunks(const SapArgs &a, const RowMeta &r,
     }
 }
 
-// One row of a string projected onto y in LDS (the row's first PF chunks prefetched in
-// cc / cv); the adds are LDS atomics, since the entries of a row may share a voxel.
-template <typename VT, int PF>
-__device__ __forceinline__ void project_row(const SapArgs &a, float *y, const RowMeta &r, const int32_t (&cc)[PF],
-                                            const typename RawOf<VT>::T (&cv)[PF], int lane) {
-    if (r.coef == 0.0f) return;
+// One row of a string projected onto y in LDS with the first NC of the PF prefetched
+// chunks in cc / cv (the row holds no entry past them unless NC = PF); the adds are LDS
+// atomics, since the entries of a row may share a voxel.
+template <typename VT, int PF, int NC>
+__device__ __forceinline__ void project_chunks(const SapArgs &a, float *y, const RowMeta &r, uint32_t len,
+                                               const int32_t (&cc)[PF], const typename RawOf<VT>::T (&cv)[PF],
+                                               int lane) {
     const uint32_t n = (uint32_t)a.n;
-    const int64_t len64 = r.end - r.beg;   // a row is shorter than 2^31 entries
-    const uint32_t len = len64 < 0x7fffffff ? (uint32_t)len64 : 0x7fffffffu;
-    bool ok[PF];
+    bool ok[NC];
 #pragma unroll
-    for (int k = 0; k < PF; ++k) ok[k] = (uint32_t)(k * 64 + lane) < len && (uint32_t)cc[k] < n;
-    // all gathers of the prefetched chunks in flight before the first use; an entry past
-    // the row or with a bad column reads y[0] and counts 0
-    float yv[PF];
+    for (int k = 0; k < NC; ++k) ok[k] = (uint32_t)(k * 64 + lane) < len && (uint32_t)cc[k] < n;
+    // all gathers in flight before the first use; an entry past the row or with a bad
+    // column reads y[0] and counts 0
+    float yv[NC];
 #pragma unroll
-    for (int k = 0; k < PF; ++k) yv[k] = y[ok[k] ? cc[k] : 0];
+    for (int k = 0; k < NC; ++k) yv[k] = y[ok[k] ? cc[k] : 0];
     double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < PF; ++k) acc = fma((double)(ok[k] ? widen(cv[k]) : 0.0f), (double)yv[k], acc);
-    const bool tail = len > (uint32_t)(PF * 64);   // uniform
+    for (int k = 0; k < NC; ++k) acc = fma((double)(ok[k] ? widen(cv[k]) : 0.0f), (double)yv[k], acc);
+    const bool tail = NC == PF && len > (uint32_t)(PF * 64);   // uniform
     if (tail) {
         for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
             const int32_t c = a.cols[e];
@@ -262,7 +266,7 @@ __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const Ro
     const float alpha = (float)(((double)r.b - dot) * (double)fabsf(r.coef));
     // no branch: an entry that is not the row's adds 0 to its lane's spare slot past y
 #pragma unroll
-    for (int k = 0; k < PF; ++k)
+    for (int k = 0; k < NC; ++k)
         atomicAdd(y + (ok[k] ? (uint32_t)cc[k] : n + (uint32_t)lane), ok[k] ? alpha * widen(cv[k]) : 0.0f);
     if (tail) {
         for (int64_t e = r.beg + PF * 64 + lane; e < r.end; e += 64) {
@@ -270,6 +274,21 @@ __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const Ro
             if ((uint32_t)c < n) atomicAdd(y + c, alpha * val_at<VT>(a.vals, e));
         }
     }
+}
+
+template <typename VT, int PF>
+__device__ __forceinline__ void project_row(const SapArgs &a, float *y, const RowMeta &r, const int32_t (&cc)[PF],
+                                            const typename RawOf<VT>::T (&cv)[PF], int lane) {
+    static_assert(0 < SAP_T1 && SAP_T1 < SAP_T2 && SAP_T2 < PF, "tiers");
+    if (r.coef == 0.0f) return;
+    const int64_t len64 = r.end - r.beg;   // a row is shorter than 2^31 entries
+    const uint32_t len = len64 < 0x7fffffff ? (uint32_t)len64 : 0x7fffffffu;
+    if (len <= (uint32_t)(SAP_T1 * 64))
+        project_chunks<VT, PF, SAP_T1>(a, y, r, len, cc, cv, lane);
+    else if (len <= (uint32_t)(SAP_T2 * 64))
+        project_chunks<VT, PF, SAP_T2>(a, y, r, len, cc, cv, lane);
+    else
+        project_chunks<VT, PF, PF>(a, y, r, len, cc, cv, lane);
 }
 
 // Metadata of 64 consecutive string positions, one per lane.
