@@ -16,10 +16,10 @@
 // strings; one wavefront walks a row's entries 64 at a time.
 //
 // LDS iterate: the rows' metadata is loaded 64 rows at a time (one row per lane) and the
-// first 384 entries of the next eight rows are always in flight, so the wave waits on the
+// first 384 entries of the next four rows are always in flight, so the wave waits on the
 // latency of HBM only once per several rows.  With one wave on its SIMD, every issued
 // instruction costs the wave its full issue slot, so a row is projected with only as many
-// chunks of 64 entries as it spans (2, 4 or 6; a uniform branch on its length).
+// chunks of 64 entries as it spans (a uniform branch on its length picks the body).
 //
 // Workspace iterate: each row update ends with a wait for its writes to y, and the
 // vector-memory counter retires in issue order, so that wait would also drain any row
@@ -45,11 +45,8 @@ constexpr int SAP_HASH = 1 << SAP_HASH_BITS;
 // Ring of rows in flight: D rows ahead, the first PF chunks of 64 entries of each.  The
 // LDS iterate takes short rows from a long ring; the workspace iterate (large grids, long
 // curved rows) takes longer rows from a shorter ring.
-template <bool LDS> struct Ring { static constexpr int D = 8, PF = 6; };
+template <bool LDS> struct Ring { static constexpr int D = 4, PF = 6; };
 template <> struct Ring<false> { static constexpr int D = 2, PF = 12; };
-// Chunk counts of the LDS iterate's shorter row bodies (a row of at most 64 * T1 entries
-// takes T1 chunks, else one of at most 64 * T2 takes T2, else PF).
-constexpr int SAP_T1 = 2, SAP_T2 = 4;
 
 struct SapLayout {
     size_t coef_off, w_off, y_off, total;
@@ -279,16 +276,19 @@ __device__ __forceinline__ void project_chunks(const SapArgs &a, float *y, const
 template <typename VT, int PF>
 __device__ __forceinline__ void project_row(const SapArgs &a, float *y, const RowMeta &r, const int32_t (&cc)[PF],
                                             const typename RawOf<VT>::T (&cv)[PF], int lane) {
-    static_assert(0 < SAP_T1 && SAP_T1 < SAP_T2 && SAP_T2 < PF, "tiers");
+    static_assert(PF == 6, "one body per chunk count");
     if (r.coef == 0.0f) return;
     const int64_t len64 = r.end - r.beg;   // a row is shorter than 2^31 entries
     const uint32_t len = len64 < 0x7fffffff ? (uint32_t)len64 : 0x7fffffffu;
-    if (len <= (uint32_t)(SAP_T1 * 64))
-        project_chunks<VT, PF, SAP_T1>(a, y, r, len, cc, cv, lane);
-    else if (len <= (uint32_t)(SAP_T2 * 64))
-        project_chunks<VT, PF, SAP_T2>(a, y, r, len, cc, cv, lane);
-    else
-        project_chunks<VT, PF, PF>(a, y, r, len, cc, cv, lane);
+    switch ((len + 63) / 64) {   // chunks the row spans (a row with coefficient != 0 has one)
+    case 0: break;
+    case 1: project_chunks<VT, PF, 1>(a, y, r, len, cc, cv, lane); break;
+    case 2: project_chunks<VT, PF, 2>(a, y, r, len, cc, cv, lane); break;
+    case 3: project_chunks<VT, PF, 3>(a, y, r, len, cc, cv, lane); break;
+    case 4: project_chunks<VT, PF, 4>(a, y, r, len, cc, cv, lane); break;
+    case 5: project_chunks<VT, PF, 5>(a, y, r, len, cc, cv, lane); break;
+    default: project_chunks<VT, PF, PF>(a, y, r, len, cc, cv, lane); break;
+    }
 }
 
 // Metadata of 64 consecutive string positions, one per lane.
