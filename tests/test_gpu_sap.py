@@ -133,6 +133,37 @@ def test_sap_workspace_long_rows(P, oracle, W, val_dtype):
     _close(got, _oracle_sap(oracle, sub, x1, 2, n_strings=130, relax=0.9), 1e-5)
 
 
+@pytest.mark.parametrize("val_dtype", ["f16", "f32"])
+def test_sap_lds_rows_of_every_length(P, oracle, val_dtype):
+    """A synthetic system with y in LDS (n = 20,000) whose rows hold 1 to 900 entries in
+    random distinct columns: every row body of the LDS iterate (1 to 6 chunks of 64, the
+    lengths on both sides of each chunk boundary) and rows past the six prefetched
+    chunks; some rows repeat a column; natural and permuted order, ragged strings."""
+    rng = np.random.default_rng(77)
+    n, m = 20000, 1500
+    lens = rng.integers(1, 901, m)
+    lens[:14] = [1, 63, 64, 65, 127, 128, 129, 255, 256, 383, 384, 385, 767, 900]
+    rp = np.zeros(m + 1, np.int64)
+    rp[1:] = np.cumsum(lens)
+    cols = np.concatenate([rng.choice(n, int(k), replace=False) for k in lens]).astype(np.int32)
+    for r in rng.choice(np.nonzero(lens >= 2)[0], 100, replace=False):
+        cols[rp[r + 1] - 1] = cols[rp[r]]
+    vt = np.float16 if val_dtype == "f16" else np.float32
+    vals = rng.uniform(0.05, 2.0, int(rp[-1])).astype(np.float32).astype(vt)
+    x_true = rng.uniform(0.0, 1.5, n)
+    b = np.add.reduceat(vals.astype(np.float64) * x_true[cols], rp[:-1]).astype(np.float32)
+    sd = dict(row_ptr=rp, cols=cols, vals=vals, b=b, n=n)
+    assert (n + 64) * 4 <= 160 * 1024
+    x0 = rng.uniform(0.0, 1.5, n)
+    got, st = _gpu_sap(P, sd, x0, 2, n_strings=7, relax=0.8)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, sd, x0, 2, n_strings=7, relax=0.8), 1e-5)
+    order = rng.permutation(m)
+    got, st = _gpu_sap(P, sd, x0, 1, n_strings=33, relax=1.3, order=order)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, sd, x0, 1, n_strings=33, relax=1.3, order=order), 1e-5)
+
+
 @pytest.mark.parametrize("grid", [(64, 48, 3.0), (300, 260, 0.7)])
 def test_sap_repeated_columns(P, oracle, W, grid):
     """Rows that hold a column twice (as a path that re-enters a voxel would): every entry
