@@ -164,6 +164,27 @@ def test_sap_lds_rows_of_every_length(P, oracle, val_dtype):
     _close(got, _oracle_sap(oracle, sd, x0, 1, n_strings=33, relax=1.3, order=order), 1e-5)
 
 
+@pytest.mark.parametrize("n", [40896, 40897])
+def test_sap_at_the_lds_limit(P, oracle, n):
+    """n on both sides of the LDS limit: 4 (n + 64) bytes = 160 KiB at n = 40,896 (the
+    iterate in LDS), one more column and it lives in the workspace.  Synthetic rows of 1
+    to 500 entries whose columns include the last ones."""
+    rng = np.random.default_rng(n)
+    m = 600
+    lens = rng.integers(1, 501, m)
+    rp = np.zeros(m + 1, np.int64)
+    rp[1:] = np.cumsum(lens)
+    cols = np.concatenate([rng.choice(n, int(k), replace=False) for k in lens]).astype(np.int32)
+    cols[rp[:-1][:50]] = n - 1   # the last column in the first entry of 50 rows
+    vals = rng.uniform(0.05, 2.0, int(rp[-1])).astype(np.float32)
+    b = np.add.reduceat(vals.astype(np.float64) * rng.uniform(0.0, 1.5, n)[cols], rp[:-1]).astype(np.float32)
+    sd = dict(row_ptr=rp, cols=cols, vals=vals, b=b, n=n)
+    x0 = rng.uniform(0.0, 1.5, n)
+    got, st = _gpu_sap(P, sd, x0, 2, n_strings=5, relax=0.9)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, sd, x0, 2, n_strings=5, relax=0.9), 1e-5)
+
+
 @pytest.mark.parametrize("grid", [(64, 48, 3.0), (300, 260, 0.7)])
 def test_sap_repeated_columns(P, oracle, W, grid):
     """Rows that hold a column twice (as a path that re-enters a voxel would): every entry
