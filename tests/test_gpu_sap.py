@@ -78,6 +78,18 @@ def test_sap_lds_path_paper_grid(P, oracle, W):
         _close(got, _oracle_sap(oracle, s, x0, K, n_strings=100, relax=0.1), 1e-5)
 
 
+def test_sap_paper_system_full_size(P, oracle, W):
+    """The benchmark's SAP workload at its full size: the paper's 200 x 160 system with
+    m = 20n = 640,000 straight rows (104M entries, traced by the oracle, binary32 values),
+    M = 100 strings, lambda = 0.1, two iterations from x = 0, y in LDS."""
+    s = _paper_sys(oracle, W, m_mult=20)
+    assert len(s["row_ptr"]) - 1 == 640_000
+    x0 = np.zeros(s["n"])
+    got, st = _gpu_sap(P, s, x0, 2, n_strings=100, relax=0.1)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, s, x0, 2, n_strings=100, relax=0.1), 1e-5)
+
+
 def test_sap_fp16_values(P, oracle, W):
     s = _paper_sys(oracle, W, 2, "f16")
     x0 = np.full(s["n"], 0.5)
