@@ -90,6 +90,20 @@ def test_sap_paper_system_full_size(P, oracle, W):
     _close(got, _oracle_sap(oracle, s, x0, 2, n_strings=100, relax=0.1), 1e-5)
 
 
+def test_sap_c1_grid_workspace(P, oracle, W):
+    """The benchmark's c1 SAP setting on an eighth of its protons: the 400 x 400 grid of
+    0.5 mm (the iterate in the workspace), 368,640 curved rows traced by the oracle,
+    binary16 values, M = 100 strings, lambda = 0.1, two iterations from x = 0."""
+    cfg = W.c1()
+    bm = dict(cfg["beam"], n_protons=cfg["beam"]["n_protons"] // 8)
+    s = _system(oracle, W, cfg["phantom"], bm, "f16")
+    assert len(s["row_ptr"]) - 1 == 368_640 and s["n"] * 4 > 160 * 1024
+    x0 = np.zeros(s["n"])
+    got, st = _gpu_sap(P, s, x0, 2, n_strings=100, relax=0.1)
+    assert st == 0
+    _close(got, _oracle_sap(oracle, s, x0, 2, n_strings=100, relax=0.1), 1e-5)
+
+
 def test_sap_fp16_values(P, oracle, W):
     s = _paper_sys(oracle, W, 2, "f16")
     x0 = np.full(s["n"], 0.5)
