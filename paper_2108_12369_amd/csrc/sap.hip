@@ -3,7 +3,9 @@
 //
 //   pct_sap_prepare : k_sap_prepare   one wavefront per row: checks its bounds and
 //                                     columns, coefficient lambda / ||a_i||^2 (FP64 sum),
-//                                     negated for a row that holds a column twice
+//                                     negated for a row that holds a column twice (found
+//                                     with a column bitmap in LDS, or a hash table when
+//                                     n is large)
 //   pct_sap_iterate : k_sap_string    one wavefront per string, y in LDS (when n floats
 //                                     fit): y = x_k, then the relaxed projection of every
 //                                     row of the string in order; y_t to the workspace
@@ -130,28 +132,80 @@ __device__ __forceinline__ bool seen_before(unsigned long long *tab, uint32_t ta
 // binary64.  A row that holds some column more than once (a curved path can re-enter a
 // voxel), or is too long for the column table, gets its coefficient negated: the
 // workspace iterate then adds its updates atomically instead of storing them.
-template <typename VT>
+// BITS: the repeats are found with a bitmap of the n columns per wave in dynamic LDS
+// (one atomic OR per entry, then the row's words cleared) instead of the hash table.
+template <typename VT, bool BITS>
 __global__ __launch_bounds__(64 * SAP_WAVES_PREP) void k_sap_prepare(SapArgs a, float relax) {
-    __shared__ unsigned long long tabs[SAP_WAVES_PREP][SAP_HASH];
+    extern __shared__ uint32_t bitmaps[];
     const int lane = threadIdx.x & 63;
-    unsigned long long *tab = tabs[threadIdx.x >> 6];
-    for (int j = lane; j < SAP_HASH; j += 64) tab[j] = ~0ull;   // tag 0xffffffff: never a row's
+    unsigned long long *tab = nullptr;
+    uint32_t *bm = nullptr;
+    if constexpr (BITS) {
+        const uint32_t words = ((uint32_t)a.n + 31u) / 32u;
+        bm = bitmaps + (size_t)(threadIdx.x >> 6) * words;
+        for (uint32_t j = lane; j < words; j += 64) bm[j] = 0u;
+    } else {
+        __shared__ unsigned long long tabs[SAP_WAVES_PREP][SAP_HASH];
+        tab = tabs[threadIdx.x >> 6];
+        for (int j = lane; j < SAP_HASH; j += 64) tab[j] = ~0ull;   // tag 0xffffffff: never a row's
+    }
     const int64_t wid = (int64_t)blockIdx.x * SAP_WAVES_PREP + (threadIdx.x >> 6);
     const int64_t nw = (int64_t)gridDim.x * SAP_WAVES_PREP;
     uint32_t tag = 0;
     for (int64_t i = wid; i < a.m; i += nw, ++tag) {
         const int64_t beg = a.row_ptr[i], end = a.row_ptr[i + 1];
         bool ok = beg >= 0 && end >= beg && end <= a.nnz;
-        const bool hashable = ok && end - beg <= SAP_HASH / 2;
+        const bool hashable = BITS || (ok && end - beg <= SAP_HASH / 2);
         bool dup = false;
         double nrm = 0.0;
         if (ok) {
-            for (int64_t e = beg + lane; e < end; e += 64) {
-                const int32_t c = a.cols[e];
-                ok = ok && (uint32_t)c < (uint32_t)a.n;
-                const double v = (double)val_at<VT>(a.vals, e);
-                nrm = fma(v, v, nrm);
-                if (hashable && seen_before(tab, tag, c)) dup = true;
+            // eight chunks of 64 entries loaded before any is used, so that a row's loads
+            // overlap (the wave has little else to hide their latency); a row of at most
+            // 512 entries is cleared from the columns still in registers
+            constexpr int U = 8;
+            const bool one_pass = end - beg <= 64 * U;   // uniform
+            int32_t cu[U];
+            float vu[U];
+            for (int64_t e0 = beg + lane; e0 < end; e0 += 64 * U) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t e = e0 + u * 64;
+                    cu[u] = e < end ? a.cols[e] : 0;
+                    vu[u] = e < end ? val_at<VT>(a.vals, e) : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (e0 + u * 64 < end) {
+                        const int32_t c = cu[u];
+                        const bool okc = (uint32_t)c < (uint32_t)a.n;
+                        ok = ok && okc;
+                        const double v = (double)vu[u];
+                        nrm = fma(v, v, nrm);
+                        if constexpr (BITS) {
+                            if (okc) {
+                                const uint32_t bit = 1u << ((uint32_t)c & 31u);
+                                if (atomicOr(bm + ((uint32_t)c >> 5), bit) & bit) dup = true;
+                            }
+                        } else {
+                            if (hashable && seen_before(tab, tag, c)) dup = true;
+                        }
+                    }
+                }
+            }
+            if constexpr (BITS) {
+                // the row's words back to zero (the wave's LDS accesses are in order)
+                __builtin_amdgcn_wave_barrier();
+                if (one_pass) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (beg + lane + u * 64 < end && (uint32_t)cu[u] < (uint32_t)a.n) bm[(uint32_t)cu[u] >> 5] = 0u;
+                } else {
+                    for (int64_t e = beg + lane; e < end; e += 64) {
+                        const int32_t c = a.cols[e];
+                        if ((uint32_t)c < (uint32_t)a.n) bm[(uint32_t)c >> 5] = 0u;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
             }
         }
         const bool all_ok = __builtin_amdgcn_ballot_w64(!ok) == 0;
@@ -608,10 +662,27 @@ pct_status pct_sap_prepare(const pct_csr *A, const pct_sap *p, void *ws_dev, siz
     if (A->n_rows > 0) {
         const int64_t blocks64 = (A->n_rows + SAP_WAVES_PREP - 1) / SAP_WAVES_PREP;
         const unsigned blocks = (unsigned)(blocks64 < 65536 ? blocks64 : 65536);
-        if (A->val_dtype == PCT_F16)
-            hipLaunchKernelGGL((k_sap_prepare<__half>), dim3(blocks), dim3(64 * SAP_WAVES_PREP), 0, s, a, p->relax);
-        else
-            hipLaunchKernelGGL((k_sap_prepare<float>), dim3(blocks), dim3(64 * SAP_WAVES_PREP), 0, s, a, p->relax);
+        // a column bitmap per wave when two blocks of them fit a CU's LDS, else the hash
+        const size_t bm_bytes = (size_t)SAP_WAVES_PREP * (((size_t)A->n_cols + 31) / 32) * sizeof(uint32_t);
+        const bool bits = 2 * bm_bytes <= lds_limit();
+        if (bits) {
+            const void *k = A->val_dtype == PCT_F16 ? (const void *)k_sap_prepare<__half, true>
+                                                    : (const void *)k_sap_prepare<float, true>;
+            if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bm_bytes) != hipSuccess)
+                return PCT_EHIP;
+            if (A->val_dtype == PCT_F16)
+                hipLaunchKernelGGL((k_sap_prepare<__half, true>), dim3(blocks), dim3(64 * SAP_WAVES_PREP), bm_bytes, s,
+                                   a, p->relax);
+            else
+                hipLaunchKernelGGL((k_sap_prepare<float, true>), dim3(blocks), dim3(64 * SAP_WAVES_PREP), bm_bytes, s,
+                                   a, p->relax);
+        } else if (A->val_dtype == PCT_F16) {
+            hipLaunchKernelGGL((k_sap_prepare<__half, false>), dim3(blocks), dim3(64 * SAP_WAVES_PREP), 0, s, a,
+                               p->relax);
+        } else {
+            hipLaunchKernelGGL((k_sap_prepare<float, false>), dim3(blocks), dim3(64 * SAP_WAVES_PREP), 0, s, a,
+                               p->relax);
+        }
     }
     return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
 }
