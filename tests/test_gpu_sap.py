@@ -211,11 +211,13 @@ def test_sap_at_the_lds_limit(P, oracle, n):
     _close(got, _oracle_sap(oracle, sd, x0, 2, n_strings=5, relax=0.9), 1e-5)
 
 
-@pytest.mark.parametrize("grid", [(64, 48, 3.0), (300, 260, 0.7)])
+@pytest.mark.parametrize("grid", [(64, 48, 3.0), (300, 260, 0.7), (460, 400, 0.45)])
 def test_sap_repeated_columns(P, oracle, W, grid):
     """Rows that hold a column twice (as a path that re-enters a voxel would): every entry
     counts in the dot product, the norm and the update, with y in LDS (64 x 48) and in the
-    workspace (300 x 260, where such rows take atomic adds and the others plain stores)."""
+    workspace (300 x 260 and 460 x 400, where such rows take atomic adds and the others
+    plain stores).  The prepare pass finds the repeats with a column bitmap up to 163,840
+    columns and with a hash table above (460 x 400 = 184,000)."""
     nx, ny, h = grid
     ph = W.phantom(2, (nx, ny), (h, h), W.neo1_regions())
     bm = W.beam(560, 20, 9.0, 2000, (-90.0, 90.0), path="hermite", sigma_in=0.01, sigma_out=0.01,
