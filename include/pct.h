@@ -247,7 +247,10 @@ pct_status pct_graph_destroy(pct_graph graph);
  * string starts from y = x_k and applies, row after row,
  *     y <- y + lambda (b_i - <a_i, y>) / ||a_i||^2 a_i     (rows with ||a_i|| = 0 skipped),
  * and x_{k+1} = sum_t w_t y_t.  This is the usual Kaczmarz sign with the current y in
- * the residual; the printed update uses x_k and the opposite sign.
+ * the residual; the printed update uses x_k and the opposite sign.  a_i is the row as a
+ * vector of R^n: entries of a row that share a column add into that one component (in
+ * ||a_i||^2 as in <a_i, y> and the update), so the result does not depend on whether the
+ * caller stores a column once or as several entries.
  * Arithmetic: y in binary32, <a_i, y> and ||a_i||^2 accumulated in binary64, the
  * weighted sum over strings in binary64 in string order (deterministic). */
 typedef struct {
@@ -284,7 +287,8 @@ pct_status pct_sap_prepare(const pct_csr *A, const pct_sap *p, void *ws_dev, siz
  * after pct_sap_prepare on the same A, parameters and workspace.  Each string is one
  * workgroup.  Its iterate lives in LDS when n binary32 fit a workgroup's LDS (one
  * wavefront), else in the workspace (one wavefront loads the rows, one projects them).
- * A row's entries are all applied, also where a column repeats in the row. */
+ * A row's entries are all applied, also where a column repeats in the row; ||a_i|| is
+ * then the norm of their sum per column. */
 pct_status pct_sap_iterate(const pct_csr *A, const pct_sap *p, float *x_dev, int32_t n_iter, void *ws_dev,
                            size_t ws_bytes, void *stream);
 

@@ -732,15 +732,23 @@ int32_t or_sizeof_beam(void) { return (int32_t)sizeof(or_beam); }
  * the next iterate is the weighted sum x_{k+1} = sum_t w_t y_t.  The update uses the
  * current y, with the residual b_i - <a_i, y> (the standard Kaczmarz sign; the printed
  * update has the other sign and x_k in place of y).  Everything in binary64.
- * weights == NULL: w_t = 1/M.  order == NULL: rows in their natural order.  A row is
- * taken as stored: entries that share a column each count in the dot product, the norm
- * (sum of v^2) and the update. */
+ * weights == NULL: w_t = 1/M.  order == NULL: rows in their natural order.  ||a_i|| is
+ * the norm of the row as a vector of R^n: entries of a row that share a column (a curved
+ * path re-entering a voxel) add into that one component, so the squared norm is the sum
+ * over the row's distinct columns of (sum of their values)^2; the dot product and the
+ * update, taken entry by entry, act on that same vector.  With lambda = 1 a row update
+ * then lands exactly on the row's hyperplane. */
 void or_sap(int64_t m, int32_t n, const int64_t *row_ptr, const int32_t *cols, const double *vals,
             const double *b, int32_t M, double lambda, const double *weights, const int64_t *order,
             double *x, int32_t n_iter)
 {
-    double *y = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-    double *acc = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    double *y = (double *)malloc(nn * sizeof(double));
+    double *acc = (double *)malloc(nn * sizeof(double));
+    double *comp = (double *)malloc(nn * sizeof(double));    /* a_i as a vector of R^n */
+    int64_t *mark = (int64_t *)malloc(nn * sizeof(int64_t)); /* row whose component comp[j] holds */
+    for (size_t j = 0; j < nn; ++j) mark[j] = -1;
+    int64_t stamp = 0;
     for (int32_t it = 0; it < n_iter; ++it) {
         for (int32_t j = 0; j < n; ++j) acc[j] = 0.0;
         for (int32_t t = 0; t < M; ++t) {
@@ -749,9 +757,22 @@ void or_sap(int64_t m, int32_t n, const int64_t *row_ptr, const int32_t *cols, c
             for (int64_t s = s0; s < s1; ++s) {
                 const int64_t i = order ? order[s] : s;
                 double dot = 0.0, nrm = 0.0;
+                /* the components of a_i: the values of every column, summed */
+                const int64_t tag = 2 * (stamp++);
                 for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                    if (mark[cols[e]] != tag) {
+                        mark[cols[e]] = tag;
+                        comp[cols[e]] = 0.0;
+                    }
+                    comp[cols[e]] += vals[e];
                     dot += vals[e] * y[cols[e]];
-                    nrm += vals[e] * vals[e];
+                }
+                /* ||a_i||^2: each distinct column once */
+                for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                    if (mark[cols[e]] == tag) {
+                        nrm += comp[cols[e]] * comp[cols[e]];
+                        mark[cols[e]] = tag + 1;
+                    }
                 }
                 if (nrm == 0.0) continue;
                 const double alpha = lambda * (b[i] - dot) / nrm;
@@ -762,6 +783,8 @@ void or_sap(int64_t m, int32_t n, const int64_t *row_ptr, const int32_t *cols, c
         }
         for (int32_t j = 0; j < n; ++j) x[j] = acc[j];
     }
+    free(comp);
+    free(mark);
     free(y);
     free(acc);
 }

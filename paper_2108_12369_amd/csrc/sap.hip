@@ -129,9 +129,10 @@ __device__ __forceinline__ bool seen_before(unsigned long long *tab, uint32_t ta
 }
 
 // One wavefront per row: bounds and columns checked, coefficient lambda / ||a_i||^2 in
-// binary64.  A row that holds some column more than once (a curved path can re-enter a
-// voxel), or is too long for the column table, gets its coefficient negated: the
-// workspace iterate then adds its updates atomically instead of storing them.
+// binary64, the norm of the row as a vector of R^n (entries sharing a column summed into
+// one component).  A row that holds some column more than once (a curved path can
+// re-enter a voxel), or is too long for the column table, gets its coefficient negated:
+// the workspace iterate then adds its updates atomically instead of storing them.
 // BITS: the repeats are found with a bitmap of the n columns per wave in dynamic LDS
 // (one atomic OR per entry, then the row's words cleared) instead of the hash table.
 template <typename VT, bool BITS>
@@ -210,6 +211,26 @@ __global__ __launch_bounds__(64 * SAP_WAVES_PREP) void k_sap_prepare(SapArgs a, 
         }
         const bool all_ok = __builtin_amdgcn_ballot_w64(!ok) == 0;
         const bool repeats = !hashable || __builtin_amdgcn_ballot_w64(dup) != 0;
+        if (repeats && all_ok) {
+            // ||a_i||^2 of the row as a vector: entries that share a column add into one
+            // component, so the sum over entries e of v_e * (sum of the values of e's
+            // column), which counts each column's (sum of values)^2 once.  Every lane
+            // compares its entries with all of the row's (loads of a uniform index),
+            // quadratic in the row length; rows that repeat a column are few.
+            nrm = 0.0;
+            for (int64_t e0 = beg; e0 < end; e0 += 64) {
+                const int64_t e = e0 + lane;
+                const int32_t ce = e < end ? a.cols[e] : -1;
+                const double ve = e < end ? (double)val_at<VT>(a.vals, e) : 0.0;
+                double s = 0.0;
+                for (int64_t f = beg; f < end; ++f) {
+                    const int32_t cf = a.cols[f];
+                    const double vf = (double)val_at<VT>(a.vals, f);
+                    s += cf == ce ? vf : 0.0;
+                }
+                nrm = fma(ve, s, nrm);
+            }
+        }
         nrm = wave_sum(nrm);
         if (lane == 0) {
             const float cf = (all_ok && nrm > 0.0) ? (float)((double)relax / nrm) : 0.0f;

@@ -4,7 +4,11 @@ Each pin is a case where SAP reduces to something with an independent definition
   * one string per row with weights w_t: one iteration is the weighted simultaneous
     projection x + lambda sum_t w_t r_t / ||a_t||^2 a_t (Cimmino), written here with
     scipy's sparse products;
-  * lambda = 1 on a single row: the iterate lands on the row's hyperplane;
+  * lambda = 1 on a single row: the iterate lands on the row's hyperplane, also when the
+    row stores a column twice;
+  * a system whose rows store some columns as several entries gives the iterates of the
+    same matrix with those entries summed (scipy's sum_duplicates): SAP acts on the
+    matrix A, not on its storage;
   * one string, lambda = 1, a consistent square system: Kaczmarz converges to its
     solution;
   * a consistent system started at its solution stays there, for any strings, weights
@@ -69,6 +73,52 @@ def test_unit_relaxation_projects_onto_the_row():
     a = A.toarray()[0]
     k = d.dot(a) / a.dot(a)
     assert np.allclose(d, k * a, atol=1e-14)
+
+
+def _split_entries(A, seed):
+    """The same matrix with the first and about a third of the other entries of every row
+    stored as two entries of the same column (value v as v * f and v * (1 - f)), the
+    second one later in the row."""
+    rng = np.random.default_rng(seed)
+    rp, cols, vals = [0], [], []
+    for i in range(A.shape[0]):
+        c = list(A.indices[A.indptr[i]:A.indptr[i + 1]])
+        v = list(A.data[A.indptr[i]:A.indptr[i + 1]])
+        extra_c, extra_v = [], []
+        for k in range(len(c)):
+            if k == 0 or rng.uniform() < 0.35:
+                f = rng.uniform(0.2, 0.8)
+                extra_c.append(c[k])
+                extra_v.append(v[k] * (1 - f))
+                v[k] *= f
+        cols += c + extra_c
+        vals += v + extra_v
+        rp.append(len(cols))
+    return np.array(rp, np.int64), np.array(cols, np.int32), np.array(vals, np.float64)
+
+
+def test_unit_relaxation_projects_onto_a_row_with_repeated_columns():
+    A = _random_csr(1, 30, 12, 13)
+    rp, cols, vals = _split_entries(A, 14)
+    assert len(cols) > A.nnz
+    b = np.array([7.5])
+    x0 = np.random.default_rng(15).uniform(0, 1, 30)
+    x1 = O.sap(rp, cols, vals, b, 30, x0, n_strings=1, relax=1.0)
+    assert (A @ x1)[0] == pytest.approx(7.5, rel=1e-14)
+    d = x1 - x0
+    a = A.toarray()[0]
+    assert np.allclose(d, d.dot(a) / a.dot(a) * a, atol=1e-14)
+
+
+@pytest.mark.parametrize("M,relax", [(1, 1.0), (4, 0.3), (40, 1.5)])
+def test_repeated_entries_act_as_their_sum(M, relax):
+    A = _random_csr(40, 25, 8, 16)
+    rp, cols, vals = _split_entries(A, 17)
+    b = np.random.default_rng(18).uniform(0, 10, 40)
+    x0 = np.random.default_rng(19).uniform(0, 1, 25)
+    want = _sap(A, b, x0, n_strings=M, relax=relax, n_iter=3)
+    got = O.sap(rp, cols, vals, b, 25, x0, n_strings=M, relax=relax, n_iter=3)
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-12)
 
 
 def test_kaczmarz_converges_on_consistent_square_system():
