@@ -4,9 +4,13 @@ One step = the whole path over one batch: phantom voxelisation (x), count pass, 
 (row_ptr), emit pass (cols, vals and the WEPL b).  Outputs are allocated once before
 the timed region; nothing is read back inside it.
 
-Prints one JSON line: throughput in protons/s (whole job), nnz/s, the emit kernel's
-algorithmic HBM bandwidth against the 8 TB/s peak, the plain-FP32 form measured the
-same way, and the CPU oracle timed on a bounded sample of the same workload.
+The headline is the batched workload: 64 uneven jobs (2D and 3D phantoms, straight and
+curved paths) in mixed precision with FP16 stored lengths, captured as one HIP graph and
+replayed per step, against the plain FP32 single-phantom form (the same jobs one after
+another).  Prints one JSON line: throughput in protons/s (whole job), nnz/s, the emit
+pass's algorithmic HBM bandwidth against the 8 TB/s peak (HIP events on the launch
+stream), the other workloads as legs, and the CPU oracle timed on a bounded seeded
+sample of the same jobs.
 """
 from __future__ import annotations
 
@@ -29,7 +33,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", help="c0 | c1 | c2 | c3 | c4 | paper")
+    ap.add_argument("--workload", default="c3",
+                    help="headline: c3 (the batched graph; default) | c0 | c1 | c2 | c4 | paper")
+    ap.add_argument("--no-legs", action="store_true", help="skip the c1, c2 and c4 legs")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true",
@@ -121,18 +127,24 @@ class Pipeline:
         self.graph = self.P.Graph(self.emit_sets[0], self.ws, self.nnz, build_x=True)
 
     def emit_only(self, reps=3):
-        """Average emit duration (ms) per chunk, HIP events on the launch stream."""
+        """Average emit duration (ms) per chunk: eager count and emit calls, HIP events
+        around each emit call on the stream it is launched on (torch's current stream,
+        which the binding passes to the library)."""
         torch = self.torch
+        st = torch.cuda.current_stream()
         ts = []
         for _ in range(reps):
             for k in range(len(self.chunks)):
                 self.P.count_rows(self.count_sets[k], self.ws, self.nnz)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
+                e0.record(st)
                 self.P.emit_csr(self.emit_sets[k], self.ws)
-                e1.record()
+                e1.record(st)
                 e1.synchronize()
                 ts.append(e0.elapsed_time(e1))
+        st_ = self.P.device_status(self.ws)
+        if st_ != self.P.PCT_OK:
+            raise RuntimeError(f"device status {self.P.status_string(st_)}")
         return float(np.mean(ts))
 
     def step(self, emit_events=None):
@@ -192,6 +204,9 @@ def stored_traffic(kernel, workload_name):
                 and kv.get("source_digest") == digest and "traffic_bytes_per_launch" in kv:
             return float(kv["traffic_bytes_per_launch"])
     return None
+
+
+C3_NAME = "c3-64-uneven-jobs-graph"
 
 
 def workload(name, W):
@@ -280,7 +295,8 @@ def cpu_parallel(cfgs, n_rows_target, workers):
 
 def batched_vs_single(P, W, steps, warmup, tune):
     """The 64 uneven jobs of the batched workload: mixed precision in one launch set
-    captured as a HIP graph (autotuned), against plain FP32 with one call set per job."""
+    captured as a HIP graph (autotuned), against plain FP32 with one call set per job.
+    The emit pass is timed apart, with eager calls and HIP events around them."""
     import torch
     jobs = W.c3_jobs()
     out = {}
@@ -289,12 +305,13 @@ def batched_vs_single(P, W, steps, warmup, tune):
     pb.capture()
     dt, _ = time_pipeline(pb, steps, warmup)
     ms = 1e3 * dt / steps
-    emit_ms = pb.emit_only()
-    gbs = pb.bytes_emit() / (emit_ms * 1e-3) / 1e9
-    out["batched"] = {"workload": f"c3-{len(jobs)}-uneven-jobs-graph", "rows": pb.total_rows, "nnz": pb.total_nnz,
+    emit_ms = pb.emit_only(max(3, steps))
+    emit_bytes = pb.bytes_emit()
+    out["batched"] = {"workload": C3_NAME, "rows": pb.total_rows, "nnz": pb.total_nnz,
                       "protons_per_s": pb.total_rows / (ms * 1e-3), "nnz_per_s": pb.total_nnz / (ms * 1e-3),
-                      "ms_per_step": ms, "emit_ms": emit_ms, "emit_GBps": gbs, "emit_frac": gbs / HBM_PEAK_GBS,
-                      "launch": cfg, "precision": "mixed, FP16 stored lengths"}
+                      "ms_per_step": ms, "emit_ms_per_launch": emit_ms, "algorithmic_bytes_per_launch": emit_bytes,
+                      "step_algorithmic_GBps": pb.bytes_step() / (ms * 1e-3) / 1e9, "launch": cfg,
+                      "precision": "mixed, FP16 stored lengths"}
     del pb
     torch.cuda.empty_cache()
     P.set_launch_config()
@@ -308,6 +325,41 @@ def batched_vs_single(P, W, steps, warmup, tune):
     out["batched_mixed_over_plain_single"] = out["batched"]["protons_per_s"] / out["plain_single"]["protons_per_s"]
     del ps
     torch.cuda.empty_cache()
+    return out
+
+
+def workload_leg(P, W, name, steps, warmup, tune, plain=True):
+    """One workload (chunked when it has row chunks) in mixed precision, eager calls,
+    with the emit launches timed by HIP events, and the plain FP32 form beside it."""
+    import torch
+    cfgs, chunk = workload(name, W)
+    pl = Pipeline(P, cfgs, "mixed", chunk)
+    cfg = pl.autotune() if tune else P.get_launch_config()
+    dt, emit_ms = time_pipeline(pl, steps, warmup)
+    ms = 1e3 * dt / steps
+    e_ms = float(np.mean(emit_ms))
+    eb = pl.bytes_emit() / len(pl.chunks)
+    out = {"workload": cfgs[0]["name"], "rows": pl.total_rows, "nnz": pl.total_nnz, "chunks": len(pl.chunks),
+           "protons_per_s": pl.total_rows / (ms * 1e-3), "nnz_per_s": pl.total_nnz / (ms * 1e-3),
+           "ms_per_step": ms, "emit_ms_per_launch": e_ms, "algorithmic_bytes_per_launch": eb,
+           "emit_GBps": eb / (e_ms * 1e-3) / 1e9, "emit_frac": eb / (e_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "launch": cfg, "val_dtype": pl.val_dtype[0]}
+    if len(pl.chunks) > 1:
+        out["per_chunk"] = {"rows": pl.total_rows // len(pl.chunks), "ms": ms / len(pl.chunks),
+                            "protons_per_s": pl.total_rows / (ms * 1e-3)}
+        out["end_to_end"] = {"ms": ms, "protons_per_s": pl.total_rows / (ms * 1e-3)}
+    del pl
+    torch.cuda.empty_cache()
+    P.set_launch_config()
+    if plain:
+        pf = Pipeline(P, cfgs, "plain_f32", chunk, val_dtype="f32")
+        dtp, emit_p = time_pipeline(pf, steps, warmup)
+        msp = 1e3 * dtp / steps
+        out["plain_f32"] = {"protons_per_s": pf.total_rows / (msp * 1e-3), "ms_per_step": msp,
+                            "emit_ms_per_launch": float(np.mean(emit_p))}
+        out["mixed_over_plain"] = out["protons_per_s"] / out["plain_f32"]["protons_per_s"]
+        del pf
+        torch.cuda.empty_cache()
     return out
 
 
@@ -413,6 +465,14 @@ def store_probe(torch, gib=8, reps=5):
     return 4 * n / (best * 1e-3) / 1e9
 
 
+def cpu_sample_label(cfgs, nrow, nnz, secs, cores):
+    what = (f"{nrow} rows spread over the {len(cfgs)} jobs in proportion to their sizes (evenly spaced in each)"
+            if len(cfgs) > 1 else f"{nrow} evenly spaced rows")
+    return (f"{what} of the same workload ({nnz} nnz), FP64 oracle on {cores} host "
+            f"{'core' if cores == 1 else 'processes'}, {secs:.2f} s; the rate is the sample's, "
+            f"extrapolated to the whole workload as a rate")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -429,6 +489,7 @@ def main():
         par = (workers,) + cpu_parallel(cfgs0, cpu_target, workers)
     import torch
 
+    from paper_2108_12369_amd import build as B
     from paper_2108_12369_amd import pct as P
     from paper_2108_12369_amd import workloads as W
 
@@ -447,17 +508,37 @@ def main():
         return
 
     if args.sap_only:
-        print(json.dumps({"sap": sap_leg(P, W)}))
+        print(json.dumps({"sap": sap_leg(P, W), "sap_source_digest": B.source_digest("sap")}))
         return
 
     cfgs, chunk = workload(args.workload, W)
-    pl = Pipeline(P, cfgs, "mixed", chunk)
-    tuned = None if args.no_tune else pl.autotune()
-    dt, emit_ms = time_pipeline(pl, args.steps, args.warmup)
-    ms_step = 1e3 * dt / args.steps
-    rows = pl.total_rows
-    emit_launch_ms = float(np.mean(emit_ms))   # one event pair per emit launch
-    emit_bytes_launch = pl.bytes_emit() / len(pl.chunks)
+    precision = ("mixed: FP64 geometry and face ordering, FP32 lengths, FP32 partial WEPL sums folded "
+                 "in FP64, FP16 stored lengths")
+    if args.workload == "c3":
+        bt = batched_vs_single(P, W, args.steps, args.warmup, not args.no_tune)
+        head = bt["batched"]
+        ms_step, rows, nnz = head["ms_per_step"], head["rows"], head["nnz"]
+        emit_launch_ms, emit_bytes_launch = head["emit_ms_per_launch"], head["algorithmic_bytes_per_launch"]
+        wname = C3_NAME
+        config = {"workload": wname, "jobs": len(cfgs), "rows": rows, "nnz": nnz, "chunks": 1,
+                  "val_dtype": "f16", "graph": True, "launch": head["launch"]}
+        step_gbps = head["step_algorithmic_GBps"]
+    else:
+        pl = Pipeline(P, cfgs, "mixed", chunk)
+        tuned = None if args.no_tune else pl.autotune()
+        dt, emit_ms = time_pipeline(pl, args.steps, args.warmup)
+        ms_step = 1e3 * dt / args.steps
+        rows, nnz = pl.total_rows, pl.total_nnz
+        emit_launch_ms = float(np.mean(emit_ms))   # one event pair per emit launch
+        emit_bytes_launch = pl.bytes_emit() / len(pl.chunks)
+        wname = cfgs[0]["name"]
+        config = {"workload": wname, "jobs": len(cfgs), "rows": rows, "nnz": nnz, "chunks": len(pl.chunks),
+                  "val_dtype": pl.val_dtype[0], "graph": False, "launch": tuned or P.get_launch_config()}
+        step_gbps = pl.bytes_step() / (ms_step * 1e-3) / 1e9
+        if pl.val_dtype[0] != "f16":
+            precision = precision.replace("FP16 stored lengths", "FP32 stored lengths")
+        del pl
+        torch.cuda.empty_cache()
     achieved = emit_bytes_launch / (emit_launch_ms * 1e-3) / 1e9
     res = {
         "metric": "protons/s and CSR nnz/s (HBM GB/s % peak), batched mixed vs plain FP32",
@@ -470,28 +551,30 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "precision": "mixed: FP64 geometry and face ordering, FP32 lengths, FP64 WEPL sum, "
-                     + ("FP16" if pl.val_dtype[0] == "f16" else "FP32") + " stored lengths",
+        "dtype": "f64+f32 (mixed), f16 stored",
+        "precision": precision,
         "data": "synthetic",
-        "config": {"workload": cfgs[0]["name"] if len(cfgs) == 1 else f"c3-batched-{len(cfgs)}-jobs",
-                   "jobs": len(cfgs), "rows": rows, "nnz": pl.total_nnz, "chunks": len(pl.chunks),
-                   "val_dtype": pl.val_dtype[0], "launch": tuned or P.get_launch_config()},
-        "nnz_per_s": pl.total_nnz / (ms_step * 1e-3),
-        "step_algorithmic_GBps": pl.bytes_step() / (ms_step * 1e-3) / 1e9,
-        "roofline": {"bound": "hbm", "kernel": "k_emit_wave", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "config": config,
+        "nnz_per_s": nnz / (ms_step * 1e-3),
+        "step_algorithmic_GBps": step_gbps,
+        "source_digest": B.source_digest(),
+        "roofline": {"bound": "hbm", "kernel": "k_emit_wave",
+                     "kernels_timed": "pct_emit_csr: k_emit_wave (2D and 3D instances) and k_emit_lane",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (stored_traffic("k_emit_wave", cfgs[0]["name"]) if len(cfgs) == 1 else None),
+                     "traffic": stored_traffic("k_emit_wave", wname),
                      "emit_ms_per_launch": emit_launch_ms, "algorithmic_bytes_per_launch": emit_bytes_launch},
     }
-    del pl
-    torch.cuda.empty_cache()
+    if args.workload == "c3":
+        res["plain_single"] = bt["plain_single"]
+        res["batched_mixed_over_plain_single"] = bt["batched_mixed_over_plain_single"]
+
     if not args.no_probe:
         probe = store_probe(torch)
         res["roofline"]["store_probe_GBps"] = probe
         res["roofline"]["frac_of_store_probe"] = achieved / probe
 
-    if not args.no_plain:
+    if args.workload != "c3" and not args.no_plain:
         plf = Pipeline(P, cfgs, "plain_f32", chunk, val_dtype="f32")
         dtp, emit_p = time_pipeline(plf, args.steps, args.warmup)
         msp = 1e3 * dtp / args.steps
@@ -503,30 +586,35 @@ def main():
         del plf
         torch.cuda.empty_cache()
 
-    if not args.no_batched:
-        res.update(batched_vs_single(P, W, args.steps, args.warmup, not args.no_tune))
+    if args.workload == "c3" and not args.no_legs:
+        legs = {}
+        for name, k, w in (("c1", args.steps, args.warmup), ("c2", min(args.steps, 5), 1),
+                           ("c4", min(args.steps, 2), 1)):
+            legs[name] = workload_leg(P, W, name, k, w, not args.no_tune, plain=not args.no_plain)
+            legs[name]["roofline_traffic"] = stored_traffic("k_emit_wave", legs[name]["workload"])
+        res["legs"] = legs
 
     if not args.no_options:
         res["options"] = options_leg(P, W, max(3, args.steps // 2), 1)
 
     if not args.no_sap:
         res["sap"] = sap_leg(P, W)
+        res["sap"]["source_digest"] = B.source_digest("sap")
 
     if not args.no_io:
         res["csr_write"] = io_leg(P, W)
 
     if not args.no_cpu:
         # the sample is sized for about 12 s of single-threaded oracle time
-        nrow, nnz, secs = cpu_baseline(cfgs, cpu_target)
+        nrow, nnz1, secs = cpu_baseline(cfgs, cpu_target)
         res["cpu_baseline"] = {"value": nrow / secs, "unit": "protons/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{nrow} evenly spaced rows of the same workload ({nnz} nnz), "
-                                         f"single-threaded FP64 oracle, {secs:.1f} s",
-                               "nnz_per_s": nnz / secs, "host_cpus": os.cpu_count()}
+                               "sample": cpu_sample_label(cfgs, nrow, nnz1, secs, 1),
+                               "nnz_per_s": nnz1 / secs, "host_cpus": os.cpu_count()}
         if par is not None:
             w, prow, pnnz, psecs = par
             res["cpu_baseline"]["all_cores"] = {
                 "value": prow / psecs, "unit": "protons/s", "cores": w, "nnz_per_s": pnnz / psecs,
-                "sample": f"the same {prow} rows over {w} processes, {psecs:.2f} s"}
+                "sample": cpu_sample_label(cfgs, prow, pnnz, psecs, w)}
     print(json.dumps(res))
 
 

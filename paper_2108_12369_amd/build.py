@@ -33,12 +33,17 @@ def hipcc() -> str:
     return exe
 
 
-def source_digest() -> str:
-    """Short SHA-256 over the device sources, the public header and the compiler flags:
-    identifies the kernels a stored profile was taken from."""
+def source_digest(part: str = "sim") -> str:
+    """Short SHA-256 over device sources, the public header and the compiler flags:
+    identifies the kernels a stored profile was taken from.  part "sim": the simulator
+    (every header and .hip file but the reconstruction and the file writer); "sap": the
+    reconstruction (sap.hip and the headers it includes)."""
     import hashlib
-    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
-                   if f.endswith((".hip", ".h")) and f not in ("sap.hip", "csr_io.hip"))
+    if part == "sap":
+        names = ["sap.hip", "pct_device.h", "pct_wave.h"]
+    else:
+        names = [f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")) and f not in ("sap.hip", "csr_io.hip")]
+    files = sorted(os.path.join(CSRC, f) for f in names)
     files += [os.path.join(ROOT, "include", "pct.h")]
     h = hashlib.sha256(" ".join(FLAGS).encode())
     for f in files:
