@@ -40,6 +40,7 @@ typedef int32_t pct_status;
 #define PCT_EHIP       (-5)  /* a HIP runtime call failed                               */
 #define PCT_EINTERNAL  (-6)  /* (device) emitted entries differ from the counted ones   */
 #define PCT_EIO        (-7)  /* a file could not be opened or written                   */
+#define PCT_ESCRATCH   (-8)  /* more jobs or rows than pct_wepl_static's static scratch */
 
 /* ------------------------------------------------------------------ enumerations */
 #define PCT_ELLIPSE    0   /* ellipse in the x-y plane; in 3D an elliptic cylinder along z */
@@ -193,6 +194,19 @@ pct_status pct_emit_csr(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_
  * count pass and, like pct_count_rows, clears the device status word first. */
 pct_status pct_wepl(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_t ws_bytes,
                     void *stream);
+
+/* pct_wepl without a caller workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same kernels and the same b, bit for bit, with the workspace taken from a static
+ * device array of 64 MiB per GPU (resolved on the first call on each device and held
+ * until the process ends).  The call allocates nothing, on the device or on the host.
+ * Limits: at most 64 jobs, and no more rows than pct_workspace_bytes of the jobs fits
+ * in 64 MiB (about 180,000 rows); beyond either nothing is enqueued and PCT_ESCRATCH is
+ * returned.  status_dev (device int32, nullable) receives the device status word after
+ * the call (PCT_OK, or PCT_EINTERNAL).  Every call on one GPU uses that GPU's one array:
+ * calls that overlap on one GPU (other streams, other host threads) race and must be
+ * ordered by the caller. */
+pct_status pct_wepl_static(int32_t n_jobs, const pct_job *jobs, int32_t *status_dev, void *stream);
 
 /* Synchronise the stream and return the device status word of the workspace:
  * PCT_OK, PCT_ECAPACITY or PCT_EINTERNAL (first error since the last count pass). */

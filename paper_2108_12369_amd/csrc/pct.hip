@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 namespace pct {
@@ -635,39 +636,82 @@ static double row_cost(const pct_job &jb) {
     return c;
 }
 
+// Host-side arrays of one call: on the stack for up to FIXED jobs (so that a call with
+// few jobs allocates no host memory either), on the heap beyond.
+struct HostJobs {
+    static constexpr int FIXED = 64;
+    int64_t rc_fixed[FIXED];
+    JobDev jobs_fixed[FIXED];
+    int32_t order_fixed[FIXED];
+    double cost_fixed[FIXED];
+    std::vector<int64_t> rc_heap;
+    std::vector<JobDev> jobs_heap;
+    std::vector<int32_t> order_heap;
+    std::vector<double> cost_heap;
+    int64_t *rc = rc_fixed;
+    JobDev *jobs = jobs_fixed;
+    int32_t *order = order_fixed;
+    double *cost = cost_fixed;
+    explicit HostJobs(int32_t n) {
+        if (n > FIXED) {
+            rc_heap.resize(n);
+            jobs_heap.resize(n);
+            order_heap.resize(n);
+            cost_heap.resize(n);
+            rc = rc_heap.data();
+            jobs = jobs_heap.data();
+            order = order_heap.data();
+            cost = cost_heap.data();
+        }
+    }
+    HostJobs(const HostJobs &) = delete;
+    HostJobs &operator=(const HostJobs &) = delete;
+};
+
 struct Prepared {
     Layout L;
-    std::vector<JobDev> jobs;
+    HostJobs H;
     int64_t total_etiles = 0;
+    explicit Prepared(int32_t n) : H(n) {}
 };
 
 // Job table (caller's order; the count pass uses it as is) and the emit launch order,
 // both uploaded through kernel arguments.
 static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, Prepared &P,
                           hipStream_t st) {
-    std::vector<int64_t> rc(n_jobs);
+    int64_t *rc = P.H.rc;
+    JobDev *jd = P.H.jobs;
     for (int j = 0; j < n_jobs; ++j) rc[j] = jobs[j].beam->row_count;
-    P.L = layout_of(n_jobs, rc.data());
+    P.L = layout_of(n_jobs, rc);
     if (!ws || ws_bytes < P.L.total) return PCT_EWORKSPACE;
-    P.jobs.resize(n_jobs);
     int64_t count_off = 0, tile_base = 0;
     for (int j = 0; j < n_jobs; ++j) {
-        P.jobs[j] = make_job(jobs[j], count_off, tile_base);
+        jd[j] = make_job(jobs[j], count_off, tile_base);
         count_off += rc[j];
-        tile_base += P.jobs[j].n_tiles;
+        tile_base += jd[j].n_tiles;
     }
     const pct_launch_config cfg = g_cfg;
-    std::vector<int32_t> order(n_jobs);
+    int32_t *order = P.H.order;
     for (int j = 0; j < n_jobs; ++j) order[j] = j;
     if (cfg.order == PCT_ORDER_LPT) {
-        std::vector<double> cost(n_jobs);
+        double *cost = P.H.cost;
         for (int j = 0; j < n_jobs; ++j) cost[j] = row_cost(jobs[j]);
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        if (n_jobs <= HostJobs::FIXED) {
+            // stable insertion sort: no temporary buffer
+            for (int i = 1; i < n_jobs; ++i) {
+                const int32_t v = order[i];
+                int k = i;
+                for (; k > 0 && cost[order[k - 1]] < cost[v]; --k) order[k] = order[k - 1];
+                order[k] = v;
+            }
+        } else {
+            std::stable_sort(order, order + n_jobs, [&](int a, int b) { return cost[a] > cost[b]; });
+        }
     }
     const int64_t rows_per_etile = (int64_t)(TILE / WAVE) * cfg.rows_per_wave;
     int64_t etile = 0;
     for (int k = 0; k < n_jobs; ++k) {
-        JobDev &J = P.jobs[order[k]];
+        JobDev &J = jd[order[k]];
         J.rpw = cfg.rows_per_wave;
         J.etile_base = etile;
         J.n_etiles = (J.row_count + rows_per_etile - 1) / rows_per_etile;
@@ -681,7 +725,7 @@ static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
         memset(&pack, 0, sizeof pack);
         pack.first = first;
         pack.count = (n_jobs - first < JOBS_PER_PACK) ? n_jobs - first : JOBS_PER_PACK;
-        for (int k = 0; k < pack.count; ++k) pack.jobs[k] = P.jobs[first + k];
+        for (int k = 0; k < pack.count; ++k) pack.jobs[k] = jd[first + k];
         hipLaunchKernelGGL(k_put_jobs, dim3(1), dim3(256), 0, st, dst, pack);
     }
     int32_t *odst = reinterpret_cast<int32_t *>(w + P.L.order_off);
@@ -712,6 +756,7 @@ const char *pct_status_string(pct_status s) {
         case PCT_EHIP: return "PCT_EHIP: HIP runtime error";
         case PCT_EINTERNAL: return "PCT_EINTERNAL: emitted entries differ from the count";
         case PCT_EIO: return "PCT_EIO: a file could not be opened or written";
+        case PCT_ESCRATCH: return "PCT_ESCRATCH: more jobs or rows than the static scratch of pct_wepl_static holds";
         default: return "unknown pct status";
     }
 }
@@ -769,7 +814,7 @@ pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
     if (n_jobs > 0 && !nnz_total_dev) return PCT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     if (!ws) return PCT_EWORKSPACE;
-    Prepared P;
+    Prepared P(n_jobs);
     st = prepare(n_jobs, jobs, ws, ws_bytes, P, s);
     if (st != PCT_OK) return st;
     char *w = (char *)ws;
@@ -802,7 +847,7 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
     if (n_jobs == 0) return PCT_OK;
     hipStream_t s = (hipStream_t)stream;
     if (!ws) return PCT_EWORKSPACE;
-    Prepared P;
+    Prepared P(n_jobs);
     st = prepare(n_jobs, jobs, ws, ws_bytes, P, s);
     if (st != PCT_OK) return st;
     char *w = (char *)ws;
@@ -853,6 +898,73 @@ pct_status pct_emit_csr(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws
 
 pct_status pct_wepl(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, void *stream) {
     return emit_common(n_jobs, jobs, ws, ws_bytes, stream, false);
+}
+
+}  // extern "C"
+
+namespace pct {
+// Device memory of pct_wepl_static: one array per GPU the library runs on, held until the
+// process ends.  Its address on a device comes from hipGetSymbolAddress with that device
+// current; host code uses only that address (the array's name is a host-side stand-in).
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int STATIC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[STATIC_MAX_DEVICES];
+
+// The scratch address on the device of `stream` (NULL: the current device), looked up
+// once per device.
+static pct_status static_scratch(hipStream_t stream, void **out) {
+    int cur = 0, dev = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return PCT_EHIP;
+    dev = cur;
+    if (stream) {
+        hipDevice_t d = 0;
+        if (hipStreamGetDevice(stream, &d) != hipSuccess) return PCT_EHIP;
+        dev = (int)d;
+    }
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES) return PCT_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        if (dev != cur && hipSetDevice(dev) != hipSuccess) return PCT_EHIP;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) return PCT_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PCT_OK;
+}
+
+// The status word of a workspace into the caller's int32 (PCT_OK when h is NULL).
+__global__ void k_copy_status(const WsHeader *h, int32_t *dst) {
+    if (threadIdx.x == 0) *dst = h ? h->status : PCT_OK;
+}
+}  // namespace pct
+
+extern "C" {
+
+pct_status pct_wepl_static(int32_t n_jobs, const pct_job *jobs, int32_t *status_dev, void *stream) {
+    pct_status st = check_jobs(n_jobs, jobs, false, true);
+    if (st != PCT_OK) return st;
+    if (n_jobs > HostJobs::FIXED) return PCT_ESCRATCH;
+    int64_t rc[HostJobs::FIXED];
+    for (int j = 0; j < n_jobs; ++j) rc[j] = jobs[j].beam->row_count;
+    if (layout_of(n_jobs, rc).total > STATIC_SCRATCH_BYTES) return PCT_ESCRATCH;
+    void *ws = nullptr;
+    st = static_scratch((hipStream_t)stream, &ws);
+    if (st != PCT_OK) return st;
+    st = emit_common(n_jobs, jobs, ws, STATIC_SCRATCH_BYTES, stream, false);
+    if (st != PCT_OK) return st;
+    if (status_dev) {
+        // (with no job the status word was not cleared: report OK without reading it)
+        if (n_jobs == 0) hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, (hipStream_t)stream,
+                                            (const WsHeader *)nullptr, status_dev);
+        else hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, (hipStream_t)stream, (const WsHeader *)ws,
+                                status_dev);
+    }
+    return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
 }
 
 pct_status pct_set_launch_config(const pct_launch_config *cfg) {

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpct.so")
 
 PCT_OK, PCT_EINVAL, PCT_ERANGE, PCT_ECAPACITY, PCT_EWORKSPACE, PCT_EHIP, PCT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
-PCT_EIO = -7
+PCT_EIO, PCT_ESCRATCH = -7, -8
 PCT_ELLIPSE, PCT_ELLIPSOID = 0, 1
 PCT_CORNER_AVG, PCT_CENTER, PCT_AREA_AVG = 0, 1, 2
 PCT_STRAIGHT, PCT_HERMITE = 0, 1
@@ -36,7 +36,7 @@ SCATTER = {"fixed": PCT_SCATTER_FIXED, "highland": PCT_SCATTER_HIGHLAND}
 SYMBOLS = ("pct_status_string", "pct_version", "pct_phantom_build", "pct_workspace_bytes",
            "pct_count_rows", "pct_emit_csr", "pct_wepl", "pct_device_status", "pct_set_launch_config",
            "pct_get_launch_config", "pct_autotune", "pct_graph_create", "pct_graph_launch", "pct_graph_destroy",
-           "pct_sap_workspace_bytes", "pct_sap_prepare", "pct_sap_iterate", "pct_csr_write")
+           "pct_sap_workspace_bytes", "pct_sap_prepare", "pct_sap_iterate", "pct_csr_write", "pct_wepl_static")
 
 
 class PctError(RuntimeError):
@@ -108,6 +108,8 @@ def lib():
         for name in ("pct_emit_csr", "pct_wepl"):
             getattr(L, name).argtypes = [C.c_int32, C.POINTER(Job), C.c_void_p, C.c_size_t, C.c_void_p]
             getattr(L, name).restype = C.c_int32
+        L.pct_wepl_static.argtypes = [C.c_int32, C.POINTER(Job), C.c_void_p, C.c_void_p]
+        L.pct_wepl_static.restype = C.c_int32
         L.pct_count_rows.argtypes = [C.c_int32, C.POINTER(Job), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]
         L.pct_count_rows.restype = C.c_int32
         L.pct_device_status.argtypes = [C.c_void_p, C.c_void_p]
@@ -281,6 +283,14 @@ def emit_csr(jobs: JobSet, ws: torch.Tensor, stream=None):
 def wepl(jobs: JobSet, ws: torch.Tensor, stream=None):
     n, arr = jobs.array()
     _check(lib().pct_wepl(n, arr, _ptr(ws), ws.numel(), _stream_ptr(stream)), "pct_wepl")
+
+
+def wepl_static(jobs: JobSet, status: torch.Tensor | None = None, stream=None):
+    """pct_wepl_static: b of every job without a workspace (the library's static device
+    scratch); status: optional device int32 tensor that receives the device status word."""
+    n, arr = jobs.array()
+    _check(lib().pct_wepl_static(n, arr, _ptr(status) if status is not None else None, _stream_ptr(stream)),
+           "pct_wepl_static")
 
 
 def device_status(ws: torch.Tensor, stream=None) -> int:

@@ -34,7 +34,7 @@ def test_header_functions_exported(P):
 
 
 def test_status_strings(P):
-    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         s = P.status_string(code)
         assert s.startswith("PCT_")
     assert P.lib().pct_version() >= 100
@@ -217,6 +217,31 @@ def test_job_validation(P, W):
     nnz = ptr(8)
     assert P.lib().pct_count_rows(n3, arr3, ptr(need - 1), need - 1, nnz, None) == -4
     assert P.lib().pct_count_rows(n3, arr3, None, need, nnz, None) == -4
+
+
+def test_wepl_static_limits_on_host(P, W):
+    """pct_wepl_static refuses, before touching the device: jobs without b or x
+    (PCT_EINVAL), more than 64 jobs or more rows than its 64 MiB scratch holds
+    (PCT_ESCRATCH)."""
+    fake = 1 << 20   # never dereferenced: every case below is refused on the host
+    cfg = W.c1()     # 2,949,120 rows: about 1.1 GB of workspace
+    js = P.JobSet()
+    js.add(cfg["phantom"], cfg["beam"], None)
+    n, arr = js.array()
+    assert P.lib().pct_wepl_static(n, arr, None, None) == P.PCT_EINVAL   # no b, no x
+    arr[0].x_dev = fake
+    arr[0].b_dev = fake
+    assert P.lib().pct_workspace_bytes(n, arr) > (64 << 20)
+    assert P.lib().pct_wepl_static(n, arr, None, None) == P.PCT_ESCRATCH
+    small = W.scaled(W.c0(), n_protons=90)
+    js2 = P.JobSet()
+    for _ in range(65):
+        js2.add(small["phantom"], small["beam"], None)
+    n2, arr2 = js2.array()
+    for k in range(n2):
+        arr2[k].x_dev = fake
+        arr2[k].b_dev = fake
+    assert P.lib().pct_wepl_static(n2, arr2, None, None) == P.PCT_ESCRATCH
 
 
 def test_launch_config_host_side(P):
