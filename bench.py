@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched (64 uneven jobs, one graph) vs plain single-phantom comparison")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--launch", default="",
+                    help="ROWS_PER_WAVE,ORDER: this launch configuration for the headline workload instead of "
+                         "the autotuner's pick (profiling runs, where the tuner's candidate launches would "
+                         "mix into the per-kernel figures)")
     ap.add_argument("--no-sap", action="store_true", help="skip the SAP reconstruction leg")
     ap.add_argument("--no-options", action="store_true",
                     help="skip the Highland-width and constant-chord variants of the path")
@@ -293,7 +297,17 @@ def cpu_parallel(cfgs, n_rows_target, workers):
     return sum(a for a, _ in out), sum(b for _, b in out), secs
 
 
-def batched_vs_single(P, W, steps, warmup, tune):
+def launch_config(P, pl, tune, launch):
+    """The launch configuration for a pipeline: `launch` ("rows_per_wave,order") if given,
+    else the autotuner's pick on it (or the default without tuning)."""
+    if launch:
+        rpw, order = launch.split(",")
+        P.set_launch_config(int(rpw), order.strip())
+        return P.get_launch_config()
+    return pl.autotune() if tune else P.get_launch_config()
+
+
+def batched_vs_single(P, W, steps, warmup, tune, launch="", plain=True):
     """The 64 uneven jobs of the batched workload: mixed precision in one launch set
     captured as a HIP graph (autotuned), against plain FP32 with one call set per job.
     The emit pass is timed apart, with eager calls and HIP events around them."""
@@ -301,7 +315,7 @@ def batched_vs_single(P, W, steps, warmup, tune):
     jobs = W.c3_jobs()
     out = {}
     pb = Pipeline(P, jobs, "mixed")
-    cfg = pb.autotune() if tune else P.get_launch_config()
+    cfg = launch_config(P, pb, tune, launch)
     pb.capture()
     dt, _ = time_pipeline(pb, steps, warmup)
     ms = 1e3 * dt / steps
@@ -315,6 +329,8 @@ def batched_vs_single(P, W, steps, warmup, tune):
     del pb
     torch.cuda.empty_cache()
     P.set_launch_config()
+    if not plain:
+        return out
     ps = Pipeline(P, jobs, "plain_f32", val_dtype="f32", per_job=True)
     dt, _ = time_pipeline(ps, steps, warmup)
     ms = 1e3 * dt / steps
@@ -515,7 +531,7 @@ def main():
     precision = ("mixed: FP64 geometry and face ordering, FP32 lengths, FP32 partial WEPL sums folded "
                  "in FP64, FP16 stored lengths")
     if args.workload == "c3":
-        bt = batched_vs_single(P, W, args.steps, args.warmup, not args.no_tune)
+        bt = batched_vs_single(P, W, args.steps, args.warmup, not args.no_tune, args.launch, not args.no_plain)
         head = bt["batched"]
         ms_step, rows, nnz = head["ms_per_step"], head["rows"], head["nnz"]
         emit_launch_ms, emit_bytes_launch = head["emit_ms_per_launch"], head["algorithmic_bytes_per_launch"]
@@ -525,7 +541,7 @@ def main():
         step_gbps = head["step_algorithmic_GBps"]
     else:
         pl = Pipeline(P, cfgs, "mixed", chunk)
-        tuned = None if args.no_tune else pl.autotune()
+        tuned = launch_config(P, pl, not args.no_tune, args.launch)
         dt, emit_ms = time_pipeline(pl, args.steps, args.warmup)
         ms_step = 1e3 * dt / args.steps
         rows, nnz = pl.total_rows, pl.total_nnz
@@ -533,7 +549,7 @@ def main():
         emit_bytes_launch = pl.bytes_emit() / len(pl.chunks)
         wname = cfgs[0]["name"]
         config = {"workload": wname, "jobs": len(cfgs), "rows": rows, "nnz": nnz, "chunks": len(pl.chunks),
-                  "val_dtype": pl.val_dtype[0], "graph": False, "launch": tuned or P.get_launch_config()}
+                  "val_dtype": pl.val_dtype[0], "graph": False, "launch": tuned}
         step_gbps = pl.bytes_step() / (ms_step * 1e-3) / 1e9
         if pl.val_dtype[0] != "f16":
             precision = precision.replace("FP16 stored lengths", "FP32 stored lengths")
@@ -565,7 +581,7 @@ def main():
                      "traffic": stored_traffic("k_emit_wave", wname),
                      "emit_ms_per_launch": emit_launch_ms, "algorithmic_bytes_per_launch": emit_bytes_launch},
     }
-    if args.workload == "c3":
+    if args.workload == "c3" and "plain_single" in bt:
         res["plain_single"] = bt["plain_single"]
         res["batched_mixed_over_plain_single"] = bt["batched_mixed_over_plain_single"]
 

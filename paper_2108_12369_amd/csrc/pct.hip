@@ -250,7 +250,7 @@ template <typename R, bool STORE, int DIM>
 __global__ void __launch_bounds__(TILE) k_emit_wave(const JobDev *__restrict__ jobs, const int32_t *__restrict__ eorder,
                                                     int n_jobs, char *__restrict__ rowbuf,
                                                     int32_t *__restrict__ status) {
-    __shared__ uint2 stage[TILE / WAVE][STAGE_CAP + 1];   // 1024 entries per wave
+    __shared__ __attribute__((aligned(16))) uint2 stage[TILE / WAVE][STAGE_CAP + 1];   // 1024 slots per wave
     const int64_t tile = blockIdx.x;
     const int jid = job_of_etile(jobs, eorder, n_jobs, tile);
     const JobDev &J = jobs[jid];

@@ -23,6 +23,10 @@
 // an earlier lane: its length comes from a segmented scan over the lanes, and the lane
 // that closes it writes it.  The stores of a row form one contiguous range written by
 // the whole wave.
+// A straight row in the mixed form (FP64 geometry) has no items in pass 2: each lane
+// takes its crossings directly in the order of the ray parameter, and every entry's
+// length is measured from the row's previous crossing, so there is no stitch
+// (wave_ray_row).
 //
 // The count pass (one lane per row) writes each row's description and counts its
 // entries, 1 + (face crossings), with the same item ends and the same index rule as
@@ -96,6 +100,15 @@ struct RowRef {
 };
 template <typename R, int DIM>
 using RowRefD = RowRef<R, rv_shift<DIM>()>;
+
+// A row description copied into the wave's LDS: chunk c at byte 16 c.
+struct LdsRow {
+    char *p;
+    template <class T>
+    __device__ __forceinline__ T &at(size_t off) const {
+        return *reinterpret_cast<T *>(p + off);
+    }
+};
 
 // The description of row r of job J.
 template <typename R, int DIM>
@@ -325,8 +338,8 @@ __device__ __forceinline__ void spline_windows(R c1, R c2, R c3, int N, R thr, i
 
 // The index range is kept inside the grid whatever the description holds, so that no
 // column can leave x.
-template <typename R, int DIM, int WHICH>
-__device__ __forceinline__ void lane_ray(const JobDev &J, RowRefD<R, DIM> w, LaneP<R> &p) {
+template <typename R, int DIM, int WHICH, class W>
+__device__ __forceinline__ void lane_ray(const JobDev &J, W w, LaneP<R> &p) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         p.c0[d] = RV(w, ray[WHICH].c0[d]);
@@ -345,8 +358,8 @@ __device__ __forceinline__ void lane_ray(const JobDev &J, RowRefD<R, DIM> w, Lan
     p.M = RV(w, ray[WHICH].M);
 }
 
-template <typename R, int DIM>
-__device__ __forceinline__ void lane_spline(const JobDev &J, RowRefD<R, DIM> w, LaneP<R> &p) {
+template <typename R, int DIM, class W>
+__device__ __forceinline__ void lane_spline(const JobDev &J, W w, LaneP<R> &p) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         p.c0[d] = RV(w, spl.c0[d]);
@@ -535,12 +548,17 @@ __device__ __forceinline__ float lane_prev(float v) {
 }
 
 // Entries a wavefront keeps in LDS per row (8 B each: column, FP32 length).  The slice
-// holds STAGE_CAP + 1 = 1024 entries (a power of two, so an index is kept inside it by
-// a mask); a block of four waves uses 32 KiB.
+// has STAGE_CAP + 1 = 1024 slots (a power of two, so an index is kept inside it by a
+// mask); a block of four waves uses 32 KiB, which keeps 5 blocks on a CU.  Its last
+// STAGE_DESC slots hold the wave's copy of the current row's description, so a row the
+// wave walks has at most STAGE_ROW_MAX entries.
 constexpr int STAGE_CAP = 1023;
+constexpr int STAGE_DESC = (int)(rv_bytes<double>() / 8);
+constexpr int STAGE_ROW_MAX = STAGE_CAP + 1 - STAGE_DESC;
+static_assert(rv_bytes<double>() % 16 == 0 && STAGE_ROW_MAX % 2 == 0, "the copy is 16-byte aligned");
 
 // Output of one row: the row's entries are staged in the wave's LDS slice (at most
-// STAGE_CAP; longer rows are walked by the per-lane kernel) and written out afterwards
+// STAGE_ROW_MAX; longer rows are walked by the per-lane kernel) and written out afterwards
 // in order, 64 consecutive entries per store instruction, into the row's slices of
 // cols / vals.  WEPL partial per lane in FP32 over the lane's pieces, folded into TW.
 // Pointers into device memory in the global address space: loads and stores become
@@ -548,6 +566,14 @@ constexpr int STAGE_CAP = 1023;
 // instructions, which every wait for a scalar or LDS access also waits for).
 #define PCT_GLOBAL __attribute__((address_space(1)))
 template <typename T> __device__ __forceinline__ PCT_GLOBAL T *gptr(T *p) { return (PCT_GLOBAL T *)p; }
+
+// Load of a value that no kernel of the pass writes, at an address the same in every lane,
+// through the constant address space: a scalar load, whose wait does not also wait for the
+// wave's vector stores and gathers still in flight (those share the vector memory counter,
+// which retires in issue order).
+template <typename T> __device__ __forceinline__ T load_uniform(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
 
 template <typename TW>
 struct RowOut {
@@ -563,6 +589,21 @@ struct RowOut {
     TW wacc;
     bool store, half, want_b;
     bool bad;       // a lane closed another number of entries than it counted
+    // the next row's description, fetched while this row is walked (one 16-byte chunk in
+    // each of the first dnc lanes), goes to the wave's LDS copy before this row's stores
+    // and gathers are issued: waiting for that fetch then waits for nothing newer.  The
+    // copy is written on every path through a row (again at its end: the same bytes), so
+    // that no fetch is left pending when the next one reuses its registers.
+    uint4 *dbuf;
+    uint4 dnext;
+    int dnc;
+
+    __device__ __forceinline__ void commit(int lane) {
+        asm volatile("" ::"v"(dnext.x), "v"(dnext.y), "v"(dnext.z), "v"(dnext.w));   // the fetch has landed
+        __builtin_amdgcn_wave_barrier();   // after every read of the current copy
+        if (lane < dnc) dbuf[lane] = dnext;
+        __builtin_amdgcn_wave_barrier();
+    }
 
     // Entry `rel`.  The mask keeps even an inconsistent row inside the wave's slice.
     __device__ __forceinline__ void put(int32_t rel, int32_t col, float l) {
@@ -580,7 +621,7 @@ struct RowOut {
     template <bool WB, bool HALF>
     __device__ __forceinline__ void flush_t(int n, int lane) {
         constexpr int G = 4;   // chunks of 64 entries per group
-        n = n < STAGE_CAP + 1 ? n : STAGE_CAP + 1;
+        n = n < STAGE_ROW_MAX ? n : STAGE_ROW_MAX;
         const int m = store ? (n < len ? n : len) : 0;   // entries stored
         const bool cst = chord > 0.f;
         __builtin_amdgcn_wave_barrier();
@@ -790,8 +831,8 @@ __device__ __forceinline__ int32_t col_at(const int32_t stride[3], const int I[3
 // RAY: a straight row (kind 1) with FAST: every lane takes the one ray, whose constants
 // are the same in all lanes.
 template <typename R, int DIM, typename TW, bool FAST, bool RAY = false>
-__device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int kind, RowOut<TW> &out, int lane,
-                                         int64_t &n_entries) {
+__device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, LdsRow wl, int kind, RowOut<TW> &out,
+                                         int lane, int64_t &n_entries) {
     // item counts as the count pass writes them; the bounds only matter for a
     // description it did not write (the walk then stays finite and the count check fails)
     const int mmax = J.nmax + 1;
@@ -814,14 +855,16 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int
     LaneP<R> P;
     int base = 0;
     const bool spl = !RAY && lane >= L0 && lane < L0 + Ls;
+    // each lane its piece, from the wave's LDS copy of the description (the lanes of a
+    // curved row read different pieces)
     if (RAY || lane < L0) {
-        lane_ray<R, DIM, 0>(J, w, P);
+        lane_ray<R, DIM, 0>(J, wl, P);
         base = lane * K;
     } else if (spl) {
-        lane_spline<R, DIM>(J, w, P);
+        lane_spline<R, DIM>(J, wl, P);
         base = (lane - L0) * K;
     } else {
-        lane_ray<R, DIM, 1>(J, w, P);
+        lane_ray<R, DIM, 1>(J, wl, P);
         base = (lane - L0 - Ls) * K;
     }
     P.M = RAY ? M0 : ((lane < L0) ? M0 : (spl ? Ns : (lane <= last_lane ? M1 : 0)));
@@ -949,10 +992,114 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, int
     const float Oend = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, vs), last_lane));
     const int32_t ocol = __builtin_amdgcn_readlane(wk.cur, last_lane);
     if (lane == 0) out.put(ctot, ocol, Oend);
-    out.flush(ctot + 1, lane);
-    out.fold();
     out.bad |= !lane_ok;
-    n_entries = (int64_t)ctot + 1;
+    n_entries = (int64_t)ctot + 1;   // staged; the caller writes them out
+}
+
+// Straight row (kind 1) in the mixed form, by crossings instead of items.  The lanes
+// split the items as in wave_row and count their crossings the same way (index
+// differences at the ends of their stretches), so each lane owns the same crossings.
+// A lane then takes them in the order of the ray parameter t: along axis d they lie at
+// tA_d + k / |c1_d|, k = 0 .. n_d - 1 (tA_d: the first face ahead of the stretch's
+// start), and the next one is the smallest parameter among the axes with crossings
+// left (ties keep the lower axis).  The entry closed there is as long as the step in t
+// since the row's previous crossing times the length per unit of t.  For a lane's first
+// entry that previous crossing is the nearest face behind the stretch's start (or the
+// row's start point), so no lane needs the others' lengths and there is nothing to
+// stitch.  Parameters are FP64; a parameter step is rounded to FP32 once.
+template <int DIM, typename TW>
+__device__ __forceinline__ void wave_ray_row(const JobDev &J, RowRefD<double, DIM> w, RowOut<TW> &out, int lane,
+                                             int64_t &n_entries) {
+    using R = double;
+    const int M = min(max(RV(w, ray[0].M), 0), J.nmax + 1);
+    n_entries = 0;
+    if (M == 0) return;
+    const int K = (M + WAVE - 1) / WAVE;
+    const int last_lane = (M + K - 1) / K - 1;
+    LaneP<R> P;
+    lane_ray<R, DIM, 0>(J, w, P);
+    const int base = lane * K;
+    const bool has_items = base < M;
+    const int first = has_items ? base : 0;
+    const int last = has_items ? min(base + K, M) : 0;
+    if (!has_items) {
+        P.tS = R(0);
+        P.tE = R(0);
+    }
+    // the stretch's ends (item ends first and last) and its crossings per axis
+    R Fs[3], frs[3], Fe[3], fre[3];
+    int Is[3], Ie[3];
+    piece_point<R, DIM>(P, first, R(first), Fs);
+    piece_voxel<R, DIM>(P, Fs, Is, frs);
+    piece_point<R, DIM>(P, last, R(last), Fe);
+    piece_voxel<R, DIM>(P, Fe, Ie, fre);
+    const R ta = r_fmin<R>(r_fmax<R>(R(first), P.tS), P.tE);
+    const R tb = r_fmin<R>(r_fmax<R>(R(last), P.tS), P.tE);
+    int n[3] = {0, 0, 0};
+    int c = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        n[d] = abs(Ie[d] - Is[d]);
+        c += n[d];
+    }
+    int ctot;
+    const int Pc = wave_excl_scan(c, ctot);
+
+    const int32_t stride[3] = {1, J.n[0], J.n[0] * J.n[1]};
+    R inv[3] = {R(0), R(0), R(0)}, tA[3] = {R(0), R(0), R(0)};
+    int32_t dcol[3] = {0, 0, 0};
+    R tprev = P.tS;   // the row's start point, unless a face lies between it and ta
+    float l2 = 0.f;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const R rate = fabs(P.c1[d]);   // voxels per unit of t; 1 on the dominant axis
+        const float q = (float)rate * (float)J.h[d];
+        l2 = fmaf(q, q, l2);
+        // 1 / rate: the hardware reciprocal and one Newton step (unused when rate = 0)
+        R iv = __builtin_amdgcn_rcp(rate);
+        iv = r_fma<R>(r_fma<R>(-rate, iv, R(1)), iv, iv);
+        inv[d] = iv;
+        const bool up = P.c1[d] > R(0);
+        // distance from the start to the first face ahead and to the nearest face behind
+        const R ahead = up ? R(1) - frs[d] : frs[d];
+        const R behind = up ? frs[d] : R(1) - frs[d];
+        tA[d] = r_fma<R>(ahead, iv, ta);
+        if (rate > R(0)) tprev = r_fmax<R>(tprev, r_fma<R>(-behind, iv, ta));
+        dcol[d] = up ? stride[d] : -stride[d];
+    }
+    tprev = r_fmin<R>(tprev, ta);
+    const float Lt = sqrtf(l2);   // mm per unit of t
+
+    int32_t cur = col_at<DIM>(stride, Is);
+    int k0 = 0, k1 = 0, k2 = 0;
+    R tn0 = tA[0], tn1 = tA[1], tn2 = tA[2];
+    for (int j = 0; j < c; ++j) {
+        const bool v0 = k0 < n[0], v1 = k1 < n[1];
+        const bool a1 = v1 && (!v0 || tn1 < tn0);
+        R tc = a1 ? tn1 : tn0;
+        int32_t dc = a1 ? dcol[1] : dcol[0];
+        bool a2 = false;
+        if (DIM == 3) {
+            a2 = (k2 < n[2]) && (!(v0 || v1) || tn2 < tc);
+            tc = a2 ? tn2 : tc;
+            dc = a2 ? dcol[2] : dc;
+        }
+        tc = r_fmax<R>(tc, tprev);
+        out.put(Pc + j, cur, (float)(tc - tprev) * Lt);
+        cur += dc;
+        tprev = tc;
+        k0 += (!a1 && !a2) ? 1 : 0;
+        k1 += (a1 && !a2) ? 1 : 0;
+        tn0 = r_fma<R>(R(k0), inv[0], tA[0]);
+        tn1 = r_fma<R>(R(k1), inv[1], tA[1]);
+        if (DIM == 3) {
+            k2 += a2 ? 1 : 0;
+            tn2 = r_fma<R>(R(k2), inv[2], tA[2]);
+        }
+    }
+    // the row's last entry: from its last crossing to the end point
+    if (lane == last_lane) out.put(ctot, cur, (float)r_fmax<R>(tb - tprev, R(0)) * Lt);
+    n_entries = (int64_t)ctot + 1;   // staged; the caller writes them out
 }
 
 // ------------------------------------------------------------------ row setup (one lane)
@@ -1097,7 +1244,7 @@ __device__ __forceinline__ int64_t count_row(const JobDev &J, RowRefD<R, DIM> w,
         return s.n;
     }
     const int64_t n = su.n;
-    if (n > STAGE_CAP) {
+    if (n > STAGE_ROW_MAX) {
         lane_walk = 1;
         // more entries than the wave's LDS slice holds: the per-lane walk takes the row
         RV(w, kind) = 3;
@@ -1108,45 +1255,47 @@ __device__ __forceinline__ int64_t count_row(const JobDev &J, RowRefD<R, DIM> w,
     return n;
 }
 
-// Emit pass over rows [r0, r0 + nr) of job J by one wavefront.
+// Emit pass over rows [r0, r0 + nr) of job J by one wavefront.  stage: the wave's LDS
+// slice; its last STAGE_DESC slots hold the copy of the current row's description.
 template <typename R, int DIM, bool STORE>
 __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, int64_t r0, int nr, int lane,
                                                uint2 *stage, int32_t *status) {
     using TW = typename std::conditional<std::is_same<R, double>::value, double, float>::type;
+    constexpr int NC = (int)(rv_bytes<R>() / 16);
+    static_assert(NC <= WAVE && 2 * NC <= STAGE_DESC, "a description is copied with one chunk per lane");
+    uint4 *dbuf = reinterpret_cast<uint4 *>(stage + STAGE_ROW_MAX);
     const int64_t rend = (r0 + nr < J.row_count) ? r0 + nr : J.row_count;
+    if (r0 < rend && lane < NC) dbuf[lane] = row_ref<R, DIM>(rowbuf, J, r0).template at<uint4>((size_t)lane * 16);
+    __builtin_amdgcn_wave_barrier();
+    const LdsRow wl{(char *)dbuf};
     bool bad = false;
     for (int64_t r = r0; r < rend; ++r) {
         const RowRefD<R, DIM> w = row_ref<R, DIM>(rowbuf, J, r);
-        // start fetching the next row's description (one 16-byte chunk per lane): it is
-        // in cache when the lanes load their pieces of it
-        uint4 next = make_uint4(0u, 0u, 0u, 0u);
-        constexpr int NC = (int)(rv_bytes<R>() / 16);
-        if (r + 1 < rend && lane < NC) {
-            const RowRefD<R, DIM> wn = row_ref<R, DIM>(rowbuf, J, r + 1);
-            next = wn.template at<uint4>((size_t)lane * 16);
-        }
-        const int kind = RV(w, kind);
-        if (kind == 3) continue;   // walked by the per-lane kernel
-        if (kind < 0 || kind > 3) {   // not a description of the count pass
-            if (lane == 0) set_status_dev(status, PCT_EINTERNAL);
-            continue;
-        }
         RowOut<TW> out;
+        out.dbuf = dbuf;
+        out.dnc = NC;
+        out.dnext = make_uint4(0u, 0u, 0u, 0u);
+        if (lane < NC)   // the next row's description (the last row's own at the end of the range)
+            out.dnext = row_ref<R, DIM>(rowbuf, J, r + 1 < rend ? r + 1 : r).template at<uint4>((size_t)lane * 16);
+        const int kind = RV(w, kind);
+        const bool valid = kind >= 0 && kind <= 3;
+        if (!valid && lane == 0) set_status_dev(status, PCT_EINTERNAL);   // not a description of the count pass
+        const bool mine = valid && kind != 3;   // kind 3: walked by the per-lane kernel
         out.x = gptr(J.x);
         out.wepl = 0.f;
         out.wacc = TW(0);
         out.half = (J.val_dtype == PCT_F16);
         out.want_b = (J.b != nullptr);
-        out.store = STORE;
+        out.store = STORE && mine;
         out.bad = false;
         out.stage = stage;
         out.nvox = (uint32_t)J.n[0] * (uint32_t)J.n[1] * (uint32_t)(DIM == 3 ? J.n[2] : 1);
         out.len = 0;
         out.chord = J.chord;
         int64_t pos = 0;
-        if (STORE) {
-            pos = J.row_ptr[r];
-            const int64_t end = J.row_ptr[r + 1];
+        if (out.store) {
+            pos = load_uniform(J.row_ptr + r);
+            const int64_t end = load_uniform(J.row_ptr + r + 1);
             if (pos < 0 || end < pos || end > J.cap) {
                 if (lane == 0) set_status_dev(status, PCT_ECAPACITY);
                 out.store = false;
@@ -1159,21 +1308,33 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
         out.vh = gptr((uint16_t *)J.vals + pos);
         out.vf = gptr((float *)J.vals + pos);
         int64_t ne = 0;
-        if (kind != 0) {
-            if (RV(w, fast)) {
-                if (kind == 1) wave_row<R, DIM, TW, true, true>(J, w, kind, out, lane, ne);
-                else wave_row<R, DIM, TW, true>(J, w, kind, out, lane, ne);
+        if (mine && kind != 0) {
+            if constexpr (std::is_same<R, double>::value) {
+                if (kind == 1) wave_ray_row<DIM, TW>(J, w, out, lane, ne);
+                else if (RV(w, fast)) wave_row<R, DIM, TW, true>(J, w, wl, kind, out, lane, ne);
+                else wave_row<R, DIM, TW, false>(J, w, wl, kind, out, lane, ne);
             } else {
-                wave_row<R, DIM, TW, false>(J, w, kind, out, lane, ne);
+                if (RV(w, fast)) {
+                    if (kind == 1) wave_row<R, DIM, TW, true, true>(J, w, wl, kind, out, lane, ne);
+                    else wave_row<R, DIM, TW, true>(J, w, wl, kind, out, lane, ne);
+                } else {
+                    wave_row<R, DIM, TW, false>(J, w, wl, kind, out, lane, ne);
+                }
             }
         }
-        bad |= out.bad;
-        if (out.store && ne != out.len && lane == 0) set_status_dev(status, PCT_EINTERNAL);
-        if (out.want_b) {
-            const TW bs = (TW)wave_sum((double)out.wacc);
-            if (lane == 0) J.b[r] = (float)(bs * (TW)RV(w, bfac));
+        out.commit(lane);   // every row, before its stores and gathers
+        if (ne > 0) {
+            out.flush((int)min(ne, (int64_t)STAGE_ROW_MAX), lane);
+            out.fold();
         }
-        asm volatile("" ::"v"(next.x), "v"(next.y), "v"(next.z), "v"(next.w));   // keeps the fetch; waits here
+        if (mine) {
+            bad |= out.bad;
+            if (STORE && out.store && ne != out.len && lane == 0) set_status_dev(status, PCT_EINTERNAL);
+            if (out.want_b) {
+                const TW bs = (TW)wave_sum((double)out.wacc);
+                if (lane == 0) *gptr(J.b + r) = (float)(bs * (TW)RV(w, bfac));
+            }
+        }
     }
     if (__builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) set_status_dev(status, PCT_EINTERNAL);
 }

@@ -4,9 +4,10 @@
   * the batched workload exactly as the benchmark times it -- the 64 uneven jobs captured
     with their phantom builds in one HIP graph and replayed -- on seeded rows spread over
     every job, each job's first and last rows included;
-  * rows longer than the LDS slice of a wavefront (more than 1023 entries), which the
-    count pass hands to the per-lane walk: straight and curved, FP32 and FP16, alone and
-    inside a batch with a job whose rows are short.
+  * rows longer than a wavefront stages in LDS (more than 978 entries: 1024 slots less
+    the 46 that hold the wave's copy of the row description), which the count pass hands
+    to the per-lane walk: straight and curved, FP32 and FP16, alone and inside a batch
+    with a job whose rows are short.
 
 The oracle runs on a thread pool: each call is one C call that releases the GIL.
 """
@@ -155,8 +156,8 @@ def test_rows_longer_than_the_lds_slice(P, oracle, W, path, val_dtype):
     rows = np.arange(cfg["beam"]["n_protons"], dtype=np.int64)
     g = parity.gather_rows(out["row_ptr"], out["cols"], out["vals"], out["b"], rows)
     o = _oracle_rows(oracle, cfg, rows, oracle.phantom_build(cfg["phantom"]), THREADS)
-    long_rows = int((np.diff(o["row_ptr"]) > 1023).sum())
-    print("rows over 1023 entries:", long_rows, "longest", int(np.diff(o["row_ptr"]).max()), flush=True)
+    long_rows = int((np.diff(o["row_ptr"]) > 978).sum())
+    print("rows over 978 entries:", long_rows, "longest", int(np.diff(o["row_ptr"]).max()), flush=True)
     assert long_rows > 1000
     _check(parity.compare(g, o, _h_min(cfg), val_dtype))
 
