@@ -549,16 +549,17 @@ __device__ __forceinline__ float lane_prev(float v) {
 
 // Entries a wavefront keeps in LDS per row (8 B each: column, FP32 length).  The slice
 // has STAGE_CAP + 1 = 1024 slots (a power of two, so an index is kept inside it by a
-// mask); a block of four waves uses 32 KiB, which keeps 5 blocks on a CU.  Its last
-// STAGE_DESC slots hold the wave's copy of the current row's description, so a row the
-// wave walks has at most STAGE_ROW_MAX entries.
+// mask) and a row the wave walks has at most STAGE_CAP entries; a block of four waves
+// uses 32 KiB, which keeps 5 blocks on a CU.  The last STAGE_DESC slots also hold the
+// wave's copy of the current row's description: a row of more than STAGE_ROW_MAX
+// entries overwrites it, and the next row's copy is then written after the row's stores.
 constexpr int STAGE_CAP = 1023;
 constexpr int STAGE_DESC = (int)(rv_bytes<double>() / 8);
 constexpr int STAGE_ROW_MAX = STAGE_CAP + 1 - STAGE_DESC;
 static_assert(rv_bytes<double>() % 16 == 0 && STAGE_ROW_MAX % 2 == 0, "the copy is 16-byte aligned");
 
 // Output of one row: the row's entries are staged in the wave's LDS slice (at most
-// STAGE_ROW_MAX; longer rows are walked by the per-lane kernel) and written out afterwards
+// STAGE_CAP; longer rows are walked by the per-lane kernel) and written out afterwards
 // in order, 64 consecutive entries per store instruction, into the row's slices of
 // cols / vals.  WEPL partial per lane in FP32 over the lane's pieces, folded into TW.
 // Pointers into device memory in the global address space: loads and stores become
@@ -590,16 +591,18 @@ struct RowOut {
     bool store, half, want_b;
     bool bad;       // a lane closed another number of entries than it counted
     // the next row's description, fetched while this row is walked (one 16-byte chunk in
-    // each of the first dnc lanes), goes to the wave's LDS copy before this row's stores
-    // and gathers are issued: waiting for that fetch then waits for nothing newer.  The
-    // copy is written on every path through a row (again at its end: the same bytes), so
-    // that no fetch is left pending when the next one reuses its registers.
+    // each of the first dnc lanes), is waited for before this row's stores and gathers
+    // are issued, so that the wait covers nothing newer, and on every path through the
+    // row, so that no fetch is pending when the next one reuses its registers.
     uint4 *dbuf;
     uint4 dnext;
     int dnc;
 
+    // wait for the fetch (one point on every path through a row, before its stores)
+    __device__ __forceinline__ void landed() {
+        asm volatile("" ::"v"(dnext.x), "v"(dnext.y), "v"(dnext.z), "v"(dnext.w));
+    }
     __device__ __forceinline__ void commit(int lane) {
-        asm volatile("" ::"v"(dnext.x), "v"(dnext.y), "v"(dnext.z), "v"(dnext.w));   // the fetch has landed
         __builtin_amdgcn_wave_barrier();   // after every read of the current copy
         if (lane < dnc) dbuf[lane] = dnext;
         __builtin_amdgcn_wave_barrier();
@@ -621,7 +624,7 @@ struct RowOut {
     template <bool WB, bool HALF>
     __device__ __forceinline__ void flush_t(int n, int lane) {
         constexpr int G = 4;   // chunks of 64 entries per group
-        n = n < STAGE_ROW_MAX ? n : STAGE_ROW_MAX;
+        n = n < STAGE_CAP + 1 ? n : STAGE_CAP + 1;
         const int m = store ? (n < len ? n : len) : 0;   // entries stored
         const bool cst = chord > 0.f;
         __builtin_amdgcn_wave_barrier();
@@ -1244,7 +1247,7 @@ __device__ __forceinline__ int64_t count_row(const JobDev &J, RowRefD<R, DIM> w,
         return s.n;
     }
     const int64_t n = su.n;
-    if (n > STAGE_ROW_MAX) {
+    if (n > STAGE_CAP) {
         lane_walk = 1;
         // more entries than the wave's LDS slice holds: the per-lane walk takes the row
         RV(w, kind) = 3;
@@ -1322,10 +1325,19 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
                 }
             }
         }
-        out.commit(lane);   // every row, before its stores and gathers
-        if (ne > 0) {
-            out.flush((int)min(ne, (int64_t)STAGE_ROW_MAX), lane);
+        // the next row's description: before the row's stores and gathers, unless the
+        // row's entries reach into the slots of the copy
+        out.landed();
+        if (ne <= STAGE_ROW_MAX) {
+            out.commit(lane);
+            if (ne > 0) {
+                out.flush((int)ne, lane);
+                out.fold();
+            }
+        } else {
+            out.flush((int)min(ne, (int64_t)(STAGE_CAP + 1)), lane);
             out.fold();
+            out.commit(lane);
         }
         if (mine) {
             bad |= out.bad;

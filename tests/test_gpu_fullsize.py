@@ -4,10 +4,10 @@
   * the batched workload exactly as the benchmark times it -- the 64 uneven jobs captured
     with their phantom builds in one HIP graph and replayed -- on seeded rows spread over
     every job, each job's first and last rows included;
-  * rows longer than a wavefront stages in LDS (more than 978 entries: 1024 slots less
-    the 46 that hold the wave's copy of the row description), which the count pass hands
-    to the per-lane walk: straight and curved, FP32 and FP16, alone and inside a batch
-    with a job whose rows are short.
+  * rows longer than the LDS slice of a wavefront (more than 1023 entries), which the
+    count pass hands to the per-lane walk, and rows of 979 to 1023 entries, which reach
+    into the slots that hold the wave's copy of the next row's description: straight and
+    curved, FP32 and FP16, alone and inside a batch with a job whose rows are short.
 
 The oracle runs on a thread pool: each call is one C call that releases the GIL.
 """
@@ -156,9 +156,35 @@ def test_rows_longer_than_the_lds_slice(P, oracle, W, path, val_dtype):
     rows = np.arange(cfg["beam"]["n_protons"], dtype=np.int64)
     g = parity.gather_rows(out["row_ptr"], out["cols"], out["vals"], out["b"], rows)
     o = _oracle_rows(oracle, cfg, rows, oracle.phantom_build(cfg["phantom"]), THREADS)
-    long_rows = int((np.diff(o["row_ptr"]) > 978).sum())
-    print("rows over 978 entries:", long_rows, "longest", int(np.diff(o["row_ptr"]).max()), flush=True)
+    lens = np.diff(o["row_ptr"])
+    long_rows = int((lens > 1023).sum())
+    print("rows over 1023 entries:", long_rows, "rows of 979-1023:", int(((lens > 978) & (lens <= 1023)).sum()), "longest", int(np.diff(o["row_ptr"]).max()), flush=True)
     assert long_rows > 1000
+    _check(parity.compare(g, o, _h_min(cfg), val_dtype))
+
+
+def _mid_rows_cfg(W, path, val_dtype):
+    """512 x 512 pixels of 0.375 mm (192 mm field), beams at 45 and 135 degrees with random
+    offsets in [-30, 30) mm: rows of about 800 to 1023 entries in random order, a fifth of
+    them over 978, whose entries overwrite the slots of the wave's copy of the next row's
+    description."""
+    ph = W.phantom(2, (512, 512), (0.375, 0.375), W.neo1_regions())
+    extra = dict(path="hermite", sigma_in=0.01, sigma_out=0.01, sigma_lat=1.0, step=0.375) if path == "hermite" else {}
+    bm = W.beam(778, 2, 90.0, 2000, (-30.0, 30.0), angle0_deg=45.0, noise_rel=0.01, **extra)
+    return W.workload(f"mid-rows-{path}-{val_dtype}", ph, bm, val_dtype)
+
+
+@pytest.mark.parametrize("path,val_dtype", [("straight", "f16"), ("hermite", "f16"), ("straight", "f32")])
+def test_rows_reaching_into_the_description_copy(P, oracle, W, path, val_dtype):
+    cfg = _mid_rows_cfg(W, path, val_dtype)
+    out = P.simulate(cfg)
+    rows = np.arange(cfg["beam"]["n_protons"], dtype=np.int64)
+    g = parity.gather_rows(out["row_ptr"], out["cols"], out["vals"], out["b"], rows)
+    o = _oracle_rows(oracle, cfg, rows, oracle.phantom_build(cfg["phantom"]), THREADS)
+    lens = np.diff(o["row_ptr"])
+    mid = int(((lens > 978) & (lens <= 1023)).sum())
+    print("rows of 979-1023 entries:", mid, "longest", int(lens.max()), flush=True)
+    assert mid > 200 and int((lens <= 978).sum()) > 1000 and int(lens.max()) <= 1023
     _check(parity.compare(g, o, _h_min(cfg), val_dtype))
 
 
