@@ -19,7 +19,8 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in msg["error"] and msg["gpus_requested"] == 2
 
 
-def _profile(kernel, workload):
+def _profiles():
+    out = []
     for fn in sorted(os.listdir(os.path.join(ROOT, "profiles"))):
         if not fn.endswith(".md"):
             continue
@@ -28,9 +29,29 @@ def _profile(kernel, workload):
             if line.startswith("- ") and ":" in line:
                 k, v = line[2:].split(":", 1)
                 kv[k.strip()] = v.strip()
+        if "kernel" in kv:
+            out.append(kv)
+    return out
+
+
+def _profile(kernel, workload):
+    for kv in _profiles():
         if kv.get("kernel") == kernel and kv.get("workload") == workload:
             return kv
     return None
+
+
+def test_every_stored_traffic_is_the_scaled_counters():
+    """Each profile summary's traffic is FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
+    summed over the emit call's kernels) times the copy calibration factors."""
+    kvs = _profiles()
+    assert {kv["workload"] for kv in kvs} >= {"c3-64-uneven-jobs-graph", "c1-2d-neo2-400sq-hermite"}
+    for kv in kvs:
+        kib = float(kv["fetch_kib_per_dispatch"]) * float(kv["copy_fetch_factor"]) + \
+            float(kv["write_kib_per_dispatch"]) * float(kv["copy_write_factor"])
+        got = float(kv["traffic_bytes_per_launch"])
+        assert abs(kib * 1024 - got) <= 1e-6 * got + 2048, kv["workload"]
+        assert 1.9 < float(kv["copy_fetch_factor"]) < 2.1 and 0.9 < float(kv["copy_write_factor"]) < 1.1
 
 
 def test_traffic_follows_the_source_digest(monkeypatch):
