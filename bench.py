@@ -42,7 +42,7 @@ def parse():
                     help="skip the batched (64 uneven jobs, one graph) vs plain single-phantom comparison")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--launch", default="",
-                    help="ROWS_PER_WAVE,ORDER: this launch configuration for the headline workload instead of "
+                    help="ROWS_PER_WAVE,ORDER[,BLOCKS_PER_CU]: this launch configuration for the headline workload instead of "
                          "the autotuner's pick (profiling runs, where the tuner's candidate launches would "
                          "mix into the per-kernel figures)")
     ap.add_argument("--no-sap", action="store_true", help="skip the SAP reconstruction leg")
@@ -126,9 +126,15 @@ class Pipeline:
         return self.P.autotune(self.emit_sets[0], self.ws, self.nnz)
 
     def capture(self):
-        """Record the whole step (phantoms, count, emit) in one HIP graph."""
-        assert len(self.chunks) == 1
-        self.graph = self.P.Graph(self.emit_sets[0], self.ws, self.nnz, build_x=True)
+        """Record the whole step (phantoms, count, emit) in one HIP graph: one job set, or
+        the chunk loop (every chunk's count and emit, one after another, into the same
+        outputs, whose capacity is the largest chunk's)."""
+        if len(self.chunks) == 1:
+            self.graph = self.P.Graph(self.emit_sets[0], self.ws, self.nnz, build_x=True)
+        else:
+            self.nnz_sets = self.torch.empty(sum(len(ch) for ch in self.chunks), dtype=self.torch.int64,
+                                             device="cuda")
+            self.graph = self.P.Graph(self.emit_sets, self.ws, self.nnz_sets, build_x=True)
 
     def emit_only(self, reps=3):
         """Average emit duration (ms) per chunk: eager count and emit calls, HIP events
@@ -301,8 +307,8 @@ def launch_config(P, pl, tune, launch):
     """The launch configuration for a pipeline: `launch` ("rows_per_wave,order") if given,
     else the autotuner's pick on it (or the default without tuning)."""
     if launch:
-        rpw, order = launch.split(",")
-        P.set_launch_config(int(rpw), order.strip())
+        parts = launch.split(",")
+        P.set_launch_config(int(parts[0]), parts[1].strip(), int(parts[2]) if len(parts) > 2 else 0)
         return P.get_launch_config()
     return pl.autotune() if tune else P.get_launch_config()
 
@@ -364,6 +370,15 @@ def workload_leg(P, W, name, steps, warmup, tune, plain=True):
         out["per_chunk"] = {"rows": pl.total_rows // len(pl.chunks), "ms": ms / len(pl.chunks),
                             "protons_per_s": pl.total_rows / (ms * 1e-3)}
         out["end_to_end"] = {"ms": ms, "protons_per_s": pl.total_rows / (ms * 1e-3)}
+        # the same chunk loop captured in one HIP graph (phantom once, then each chunk's
+        # count and emit), replayed per step
+        pl.capture()
+        dtg, _ = time_pipeline(pl, steps, warmup)
+        msg = 1e3 * dtg / steps
+        out["graph"] = {"ms_per_step": msg, "per_chunk_ms": msg / len(pl.chunks),
+                        "protons_per_s": pl.total_rows / (msg * 1e-3)}
+        pl.graph.close()
+        pl.graph = None
     del pl
     torch.cuda.empty_cache()
     P.set_launch_config()

@@ -224,21 +224,39 @@ pct_status pct_device_status(const void *ws_dev, void *stream);
 
 typedef struct {
     int32_t rows_per_wave;  /* 16, 32 or 64: consecutive rows walked by one wavefront    */
-    int32_t order;          /* PCT_ORDER_GIVEN | PCT_ORDER_LPT                           */
+    int32_t order;          /* PCT_ORDER_GIVEN | PCT_ORDER_LPT (within each grid          */
+                            /* dimension: the emit takes the 2D jobs, then the 3D jobs)  */
+    int32_t blocks_per_cu;  /* 0: one block of 4 wavefronts per emit tile, a grid over   */
+                            /* every tile; 1-8: a persistent grid of this many blocks    */
+                            /* per compute unit, each block taking the next tile of its  */
+                            /* grid dimension from a counter in the workspace until none */
+                            /* is left (the counters are reset by a kernel of the call,  */
+                            /* so a graph replay needs no memset)                         */
 } pct_launch_config;
 
-/* Set (NULL: reset to the default {64, PCT_ORDER_LPT}) or read the configuration. */
+/* Set (NULL: reset to the default {64, PCT_ORDER_LPT, 0}) or read the configuration. */
 pct_status pct_set_launch_config(const pct_launch_config *cfg);
 pct_status pct_get_launch_config(pct_launch_config *cfg);
 
 /* Autotuner: runs pct_count_rows once and then pct_emit_csr with every candidate
- * configuration (rows_per_wave 16/32/64 x both orders), timing each emit with HIP
- * events on `stream` (this call synchronises it), keeps the fastest as the process-wide
- * configuration and returns it in *best.  The jobs must be ready for pct_emit_csr
- * (outputs sized from an earlier count); their outputs hold a complete, valid result
- * afterwards. */
+ * configuration (rows_per_wave 16/32/64 x both orders x blocks_per_cu 0/4), timing each
+ * emit with HIP events on `stream` (this call synchronises it), keeps the fastest as the
+ * process-wide configuration and returns it in *best.  The jobs must be ready for
+ * pct_emit_csr (outputs sized from an earlier count); their outputs hold a complete,
+ * valid result afterwards.
+ * Results are cached per process, keyed by the GPU architecture, the HIP runtime version
+ * and the shape of the batch (per job: grid dimension and sizes, path, precision, value
+ * type and the row count to within a factor of two).  A call whose key is cached takes
+ * that configuration without timing (it still runs the count and the final emit).  With
+ * the environment variable PCT_TUNE_CACHE naming a file, the cache is read from it at the
+ * first call and every new result is appended to it (one line per key). */
 pct_status pct_autotune(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_t ws_bytes,
                         int64_t *nnz_total_dev, void *stream, pct_launch_config *best);
+/* The cached configuration for these jobs on the current device, if any: *found = 1 and
+ * *cfg set, else *found = 0.  Only host work. */
+pct_status pct_autotune_cached(int32_t n_jobs, const pct_job *jobs, pct_launch_config *cfg, int32_t *found);
+/* Forget every cached configuration of this process (the file is not touched). */
+pct_status pct_autotune_cache_clear(void);
 
 /* A whole batch recorded once into a HIP graph and replayed with one call: optionally
  * the voxelisation of every job's phantom into its x_dev (build_x != 0; jobs that share
@@ -250,6 +268,16 @@ pct_status pct_autotune(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_
 typedef struct pct_graph_s *pct_graph;
 pct_status pct_graph_create(int32_t n_jobs, const pct_job *jobs, int32_t build_x, void *ws_dev,
                             size_t ws_bytes, int64_t *nnz_total_dev, pct_graph *graph);
+/* The same for n_sets job sets run one after another, for instance the row chunks of one
+ * workload that reuse one set of output buffers: jobs holds the sets back to back
+ * (set_sizes[k] jobs each), and set k counts (into nnz_total_dev[off_k ...], off_k = the
+ * jobs of the sets before it) and emits after set k-1 has emitted, with one workspace
+ * large enough for every set.  The phantom builds (build_x) run once, beside the first
+ * set's count.  A set whose rows need more entries than a job's nnz_capacity sets
+ * PCT_ECAPACITY in the device status word (pct_device_status after the replay), so the
+ * capacities may come from a bound rather than from a count of every set. */
+pct_status pct_graph_create_sets(int32_t n_sets, const int32_t *set_sizes, const pct_job *jobs, int32_t build_x,
+                                 void *ws_dev, size_t ws_bytes, int64_t *nnz_total_dev, pct_graph *graph);
 pct_status pct_graph_launch(pct_graph graph, void *stream);
 pct_status pct_graph_destroy(pct_graph graph);
 

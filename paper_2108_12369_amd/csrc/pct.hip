@@ -17,7 +17,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
+#include <cstdlib>
+#include <cstring>
+#include <cstdio>
+#include <unordered_map>
 #include <vector>
 
 namespace pct {
@@ -29,8 +34,11 @@ constexpr int SCAN_THREADS = 1024;
 // per-row path descriptions
 struct WsHeader {
     int32_t status;
-    int32_t pad[63];
+    int32_t pad[31];
+    unsigned long long qnext[2];   // next emit tile of the persistent grid (2D, 3D): own cache line
+    unsigned long long pad2[14];
 };
+static_assert(sizeof(WsHeader) == 256, "the header is 256 bytes");
 
 static inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -94,6 +102,12 @@ __global__ void k_put_order(int32_t *dst, OrderPack pack) {
 
 __global__ void k_clear_status(WsHeader *h) {
     if (threadIdx.x == 0) h->status = PCT_OK;
+}
+
+// The tile counters of the persistent emit, reset by the call that uses them (a kernel,
+// so that a captured graph holds no memset node).
+__global__ void k_reset_queue(WsHeader *h) {
+    if (threadIdx.x < 2) h->qnext[threadIdx.x] = 0ull;
 }
 
 __device__ __forceinline__ void set_status(int32_t *status, int32_t code) { set_status_dev(status, code); }
@@ -259,6 +273,42 @@ __global__ void __launch_bounds__(TILE) k_emit_wave(const JobDev *__restrict__ j
     const int lane = threadIdx.x % WAVE;
     const int64_t r0 = ((tile - J.etile_base) * (TILE / WAVE) + wave) * J.rpw;
     emit_rows_wave<R, DIM, STORE>(J, rowbuf, r0, J.rpw, lane, stage[wave], status);
+}
+
+// The same work from a persistent grid: each block takes the next emit tile of its grid
+// dimension (tiles [tile_base, tile_base + n_tiles), jobs of DIM only) from the counter
+// *qnext until none is left.  Every block leaves once the counter has passed n_tiles.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename R, bool STORE, int DIM>
+__global__ void __launch_bounds__(TILE) k_emit_queue(const JobDev *__restrict__ jobs, const int32_t *__restrict__ eorder,
+                                                     int n_jobs, char *__restrict__ rowbuf, int32_t *__restrict__ status,
+                                                     unsigned long long *__restrict__ qnext, int64_t tile_base,
+                                                     int64_t n_tiles) {
+    __shared__ __attribute__((aligned(16))) uint2 stage[TILE / WAVE][STAGE_CAP + 1];   // 1024 slots per wave
+    __shared__ int64_t taken;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int lane = threadIdx.x % WAVE;
+    for (;;) {
+        if (threadIdx.x == 0) taken = (int64_t)atomicAdd(qnext, 1ull);
+        __syncthreads();
+        const int64_t k = uniform_i64(taken);
+        __syncthreads();   // every wave has read it before the next tile is taken
+        if (k >= n_tiles) break;
+        const int64_t tile = tile_base + k;
+        const int jid = job_of_etile(jobs, eorder, n_jobs, tile);
+        const JobDev &J = jobs[jid];
+        if (J.dim != DIM) {   // the tile ranges of the dimensions were laid out wrongly
+            if (threadIdx.x == 0) set_status(status, PCT_EINTERNAL);
+            continue;
+        }
+        const int64_t r0 = ((tile - J.etile_base) * (TILE / WAVE) + wave) * J.rpw;
+        emit_rows_wave<R, DIM, STORE>(J, rowbuf, r0, J.rpw, lane, stage[wave], status);
+    }
 }
 
 // Rows whose spline may leave the grid box: one lane per row.
@@ -615,11 +665,119 @@ static JobDev make_job(const pct_job &jb, int64_t count_off, int64_t tile_base) 
 }
 
 // Process-wide launch configuration of the emit pass (read-mostly).
-static pct_launch_config g_cfg = {64, PCT_ORDER_LPT};
+static constexpr pct_launch_config DEFAULT_CFG = {64, PCT_ORDER_LPT, 0};
+static pct_launch_config g_cfg = DEFAULT_CFG;
 
 static bool config_ok(const pct_launch_config &c) {
     return (c.rows_per_wave == 16 || c.rows_per_wave == 32 || c.rows_per_wave == 64) &&
-           (c.order == PCT_ORDER_GIVEN || c.order == PCT_ORDER_LPT);
+           (c.order == PCT_ORDER_GIVEN || c.order == PCT_ORDER_LPT) && c.blocks_per_cu >= 0 &&
+           c.blocks_per_cu <= 8;
+}
+
+// Compute units of the current device (queried once per device).
+static int cu_count() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
+    if (dev < 64) {
+        const int c = cache[dev].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    if (dev < 64) cache[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
+
+// ---------------------------------------------------------------- autotuner cache
+// Key: FNV-1a over the device's architecture name, the HIP runtime version and the shape
+// of the batch (per job: dimension, grid sizes, path, precision, value type, whether b is
+// written, and floor(log2(row count))).
+struct TuneCache {
+    std::mutex mu;
+    std::unordered_map<uint64_t, pct_launch_config> map;
+    bool loaded = false;
+};
+static TuneCache g_tune;
+
+static void fnv1a(uint64_t &h, const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+}
+
+static bool tune_key(int32_t n_jobs, const pct_job *jobs, uint64_t &key) {
+    static std::atomic<uint64_t> arch_hash[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return false;
+    uint64_t ah = dev < 64 ? arch_hash[dev].load(std::memory_order_relaxed) : 0;
+    if (ah == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+        int rt = 0;
+        if (hipRuntimeGetVersion(&rt) != hipSuccess) return false;
+        ah = 1469598103934665603ull;
+        fnv1a(ah, prop.gcnArchName, strnlen(prop.gcnArchName, sizeof prop.gcnArchName));
+        fnv1a(ah, &rt, sizeof rt);
+        if (ah == 0) ah = 1;
+        if (dev < 64) arch_hash[dev].store(ah, std::memory_order_relaxed);
+    }
+    uint64_t h = ah;
+    fnv1a(h, &n_jobs, sizeof n_jobs);
+    for (int j = 0; j < n_jobs; ++j) {
+        const pct_job &jb = jobs[j];
+        int64_t rc = jb.beam->row_count;
+        int32_t lg = 0;
+        while (rc > 1) {
+            rc >>= 1;
+            ++lg;
+        }
+        const int32_t f[9] = {jb.phantom->dim, jb.phantom->n[0], jb.phantom->n[1], jb.phantom->n[2], jb.beam->path,
+                              jb.precision, jb.val_dtype, jb.b_dev != nullptr ? 1 : 0, lg};
+        fnv1a(h, f, sizeof f);
+    }
+    key = h;
+    return true;
+}
+
+// The file named by PCT_TUNE_CACHE, read once: lines "<key in hex> rows_per_wave order blocks_per_cu".
+static void tune_load_locked() {
+    if (g_tune.loaded) return;
+    g_tune.loaded = true;
+    const char *path = getenv("PCT_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    unsigned long long k = 0;
+    int r = 0, o = 0, q = 0;
+    while (fscanf(f, "%llx %d %d %d", &k, &r, &o, &q) == 4) {
+        const pct_launch_config c{r, o, q};
+        if (config_ok(c)) g_tune.map[(uint64_t)k] = c;
+    }
+    fclose(f);
+}
+
+static bool tune_lookup(uint64_t key, pct_launch_config &cfg) {
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    tune_load_locked();
+    const auto it = g_tune.map.find(key);
+    if (it == g_tune.map.end()) return false;
+    cfg = it->second;
+    return true;
+}
+
+static void tune_store(uint64_t key, const pct_launch_config &cfg) {
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    tune_load_locked();
+    g_tune.map[key] = cfg;
+    const char *path = getenv("PCT_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%016llx %d %d %d\n", (unsigned long long)key, cfg.rows_per_wave, cfg.order, cfg.blocks_per_cu);
+    fclose(f);
 }
 
 // Relative cost of one row of a job: voxels a path crosses (about the sum of the grid
@@ -671,7 +829,9 @@ struct HostJobs {
 struct Prepared {
     Layout L;
     HostJobs H;
+    pct_launch_config cfg = DEFAULT_CFG;
     int64_t total_etiles = 0;
+    int64_t dim_base[2] = {0, 0}, dim_tiles[2] = {0, 0};   // emit tiles of the 2D jobs, then the 3D jobs
     explicit Prepared(int32_t n) : H(n) {}
 };
 
@@ -691,22 +851,28 @@ static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
         tile_base += jd[j].n_tiles;
     }
     const pct_launch_config cfg = g_cfg;
+    P.cfg = cfg;
     int32_t *order = P.H.order;
     for (int j = 0; j < n_jobs; ++j) order[j] = j;
-    if (cfg.order == PCT_ORDER_LPT) {
-        double *cost = P.H.cost;
-        for (int j = 0; j < n_jobs; ++j) cost[j] = row_cost(jobs[j]);
-        if (n_jobs <= HostJobs::FIXED) {
-            // stable insertion sort: no temporary buffer
-            for (int i = 1; i < n_jobs; ++i) {
-                const int32_t v = order[i];
-                int k = i;
-                for (; k > 0 && cost[order[k - 1]] < cost[v]; --k) order[k] = order[k - 1];
-                order[k] = v;
-            }
-        } else {
-            std::stable_sort(order, order + n_jobs, [&](int a, int b) { return cost[a] > cost[b]; });
+    // launch order: the 2D jobs, then the 3D jobs (so that each dimension's emit tiles are
+    // one range), each in the caller's order or costliest rows first
+    const bool lpt = cfg.order == PCT_ORDER_LPT;
+    double *cost = P.H.cost;
+    for (int j = 0; j < n_jobs; ++j) cost[j] = lpt ? row_cost(jobs[j]) : 0.0;
+    auto before = [&](int a, int b) {
+        const int da = jd[a].dim, db = jd[b].dim;
+        return da != db ? da < db : cost[a] > cost[b];
+    };
+    if (n_jobs <= HostJobs::FIXED) {
+        // stable insertion sort: no temporary buffer
+        for (int i = 1; i < n_jobs; ++i) {
+            const int32_t v = order[i];
+            int k = i;
+            for (; k > 0 && before(v, order[k - 1]); --k) order[k] = order[k - 1];
+            order[k] = v;
         }
+    } else {
+        std::stable_sort(order, order + n_jobs, before);
     }
     const int64_t rows_per_etile = (int64_t)(TILE / WAVE) * cfg.rows_per_wave;
     int64_t etile = 0;
@@ -715,6 +881,9 @@ static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
         J.rpw = cfg.rows_per_wave;
         J.etile_base = etile;
         J.n_etiles = (J.row_count + rows_per_etile - 1) / rows_per_etile;
+        const int di = J.dim == 3 ? 1 : 0;
+        if (P.dim_tiles[di] == 0) P.dim_base[di] = etile;
+        P.dim_tiles[di] += J.n_etiles;
         etile += J.n_etiles;
     }
     P.total_etiles = etile;
@@ -738,6 +907,31 @@ static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
         hipLaunchKernelGGL(k_put_order, dim3(1), dim3(256), 0, st, odst, pack);
     }
     return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
+}
+
+// The emit kernels of one call: per grid dimension either a grid over its tiles or a
+// persistent grid that takes them from a queue; then the per-lane kernel.
+template <typename R, bool STORE>
+static void launch_emit(const Prepared &P, bool has2, bool has3, hipStream_t s, const JobDev *J,
+                        const int32_t *eorder, int n_jobs, char *rb, int32_t *flags, int32_t *status, WsHeader *hdr,
+                        dim3 grid) {
+    const dim3 block(TILE);
+    if (P.cfg.blocks_per_cu > 0) {
+        hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, hdr);
+        const int64_t cap = (int64_t)cu_count() * P.cfg.blocks_per_cu;
+        const int64_t n2 = has2 ? P.dim_tiles[0] : 0, n3 = has3 ? P.dim_tiles[1] : 0;
+        if (n2 > 0)
+            hipLaunchKernelGGL((k_emit_queue<R, STORE, 2>), dim3((unsigned)(n2 < cap ? n2 : cap)), block, 0, s, J,
+                               eorder, n_jobs, rb, status, &hdr->qnext[0], P.dim_base[0], n2);
+        if (n3 > 0)
+            hipLaunchKernelGGL((k_emit_queue<R, STORE, 3>), dim3((unsigned)(n3 < cap ? n3 : cap)), block, 0, s, J,
+                               eorder, n_jobs, rb, status, &hdr->qnext[1], P.dim_base[1], n3);
+    } else {
+        const dim3 egrid((unsigned)P.total_etiles);
+        if (has2) hipLaunchKernelGGL((k_emit_wave<R, STORE, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
+        if (has3) hipLaunchKernelGGL((k_emit_wave<R, STORE, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
+    }
+    hipLaunchKernelGGL((k_emit_lane<R, STORE>), grid, block, 0, s, J, n_jobs, rb, flags, status);
 }
 
 }  // namespace pct
@@ -807,8 +1001,22 @@ size_t pct_workspace_bytes(int32_t n_jobs, const pct_job *jobs) {
     return layout_of(n_jobs, rc.data()).total;
 }
 
+}  // extern "C"
+static pct_status count_common(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes,
+                               int64_t *nnz_total_dev, void *stream, bool clear_status);
+extern "C" {
+
 pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes,
                           int64_t *nnz_total_dev, void *stream) {
+    return count_common(n_jobs, jobs, ws, ws_bytes, nnz_total_dev, stream, true);
+}
+
+}  // extern "C"
+
+// The count pass; clear_status: start the device status word afresh (every public count
+// call; a later set of a graph of sets keeps the earlier sets' errors).
+static pct_status count_common(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes,
+                               int64_t *nnz_total_dev, void *stream, bool clear_status) {
     pct_status st = check_jobs(n_jobs, jobs, true, false);
     if (st != PCT_OK) return st;
     if (n_jobs > 0 && !nnz_total_dev) return PCT_EINVAL;
@@ -818,7 +1026,7 @@ pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
     st = prepare(n_jobs, jobs, ws, ws_bytes, P, s);
     if (st != PCT_OK) return st;
     char *w = (char *)ws;
-    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, (WsHeader *)w);
+    if (clear_status) hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, (WsHeader *)w);
     if (n_jobs == 0) return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
     const JobDev *J = (const JobDev *)(w + P.L.jobs_off);
     int64_t *sums = (int64_t *)(w + P.L.sums_off);
@@ -839,6 +1047,8 @@ pct_status pct_count_rows(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
     if (T > 0) hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, offs);
     return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
 }
+
+extern "C" {
 
 static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, void *stream,
                               bool store) {
@@ -863,31 +1073,17 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
     const int32_t *eorder = (const int32_t *)(w + P.L.order_off);
     int32_t *flags = (int32_t *)(w + P.L.flags_off);
     void *rows = w + P.L.rows_off;
-    const dim3 grid((unsigned)T), egrid((unsigned)P.total_etiles), block(TILE);
+    const dim3 grid((unsigned)T);
+    char *rb = (char *)rows;
+    WsHeader *hdr = (WsHeader *)w;
     if (mixed) {
-        char *rb = (char *)rows;
         if (!store) launch_count<double, false>(has2, has3, grid, s, J, n_jobs, nullptr, nullptr, flags, rb);
-        if (store) {
-            if (has2) hipLaunchKernelGGL((k_emit_wave<double, true, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            if (has3) hipLaunchKernelGGL((k_emit_wave<double, true, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            hipLaunchKernelGGL((k_emit_lane<double, true>), grid, block, 0, s, J, n_jobs, rb, flags, status);
-        } else {
-            if (has2) hipLaunchKernelGGL((k_emit_wave<double, false, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            if (has3) hipLaunchKernelGGL((k_emit_wave<double, false, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            hipLaunchKernelGGL((k_emit_lane<double, false>), grid, block, 0, s, J, n_jobs, rb, flags, status);
-        }
+        if (store) launch_emit<double, true>(P, has2, has3, s, J, eorder, n_jobs, rb, flags, status, hdr, grid);
+        else launch_emit<double, false>(P, has2, has3, s, J, eorder, n_jobs, rb, flags, status, hdr, grid);
     } else {
-        char *rb = (char *)rows;
         if (!store) launch_count<float, false>(has2, has3, grid, s, J, n_jobs, nullptr, nullptr, flags, rb);
-        if (store) {
-            if (has2) hipLaunchKernelGGL((k_emit_wave<float, true, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            if (has3) hipLaunchKernelGGL((k_emit_wave<float, true, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            hipLaunchKernelGGL((k_emit_lane<float, true>), grid, block, 0, s, J, n_jobs, rb, flags, status);
-        } else {
-            if (has2) hipLaunchKernelGGL((k_emit_wave<float, false, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            if (has3) hipLaunchKernelGGL((k_emit_wave<float, false, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-            hipLaunchKernelGGL((k_emit_lane<float, false>), grid, block, 0, s, J, n_jobs, rb, flags, status);
-        }
+        if (store) launch_emit<float, true>(P, has2, has3, s, J, eorder, n_jobs, rb, flags, status, hdr, grid);
+        else launch_emit<float, false>(P, has2, has3, s, J, eorder, n_jobs, rb, flags, status, hdr, grid);
     }
     return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
 }
@@ -969,7 +1165,7 @@ pct_status pct_wepl_static(int32_t n_jobs, const pct_job *jobs, int32_t *status_
 
 pct_status pct_set_launch_config(const pct_launch_config *cfg) {
     if (!cfg) {
-        g_cfg = pct_launch_config{64, PCT_ORDER_LPT};
+        g_cfg = DEFAULT_CFG;
         return PCT_OK;
     }
     if (!config_ok(*cfg)) return PCT_EINVAL;
@@ -990,6 +1186,17 @@ pct_status pct_autotune(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws
     if (st != PCT_OK) return st;
     const pct_launch_config saved = g_cfg;
     hipStream_t s = (hipStream_t)stream;
+    uint64_t key = 0;
+    const bool keyed = tune_key(n_jobs, jobs, key);
+    pct_launch_config cached;
+    if (keyed && tune_lookup(key, cached)) {
+        g_cfg = cached;
+        st = pct_count_rows(n_jobs, jobs, ws, ws_bytes, nnz_total_dev, stream);
+        if (st == PCT_OK) st = pct_emit_csr(n_jobs, jobs, ws, ws_bytes, stream);   // final outputs
+        if (st != PCT_OK) g_cfg = saved;
+        *best = g_cfg;
+        return st;
+    }
     st = pct_count_rows(n_jobs, jobs, ws, ws_bytes, nnz_total_dev, stream);
     if (st != PCT_OK) return st;
     hipEvent_t e0, e1;
@@ -1000,22 +1207,25 @@ pct_status pct_autotune(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws
     }
     const int rpws[3] = {16, 32, 64};
     const int orders[2] = {PCT_ORDER_GIVEN, PCT_ORDER_LPT};
+    const int bpcs[2] = {0, 4};
     float best_ms = -1.f;
     pct_launch_config pick = saved;
-    for (int o = 0; o < 2 && st == PCT_OK; ++o) {
-        for (int r = 0; r < 3 && st == PCT_OK; ++r) {
-            g_cfg = pct_launch_config{rpws[r], orders[o]};
-            float ms = 0.f;
-            for (int rep = 0; rep < 2 && st == PCT_OK; ++rep) {
-                if (hipEventRecord(e0, s) != hipSuccess) st = PCT_EHIP;
-                if (st == PCT_OK) st = pct_emit_csr(n_jobs, jobs, ws, ws_bytes, stream);
-                if (st == PCT_OK && hipEventRecord(e1, s) != hipSuccess) st = PCT_EHIP;
-                if (st == PCT_OK && hipEventSynchronize(e1) != hipSuccess) st = PCT_EHIP;
-                if (st == PCT_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = PCT_EHIP;
-            }
-            if (st == PCT_OK && (best_ms < 0.f || ms < best_ms)) {
-                best_ms = ms;
-                pick = g_cfg;
+    for (int q = 0; q < 2 && st == PCT_OK; ++q) {
+        for (int o = 0; o < 2 && st == PCT_OK; ++o) {
+            for (int r = 0; r < 3 && st == PCT_OK; ++r) {
+                g_cfg = pct_launch_config{rpws[r], orders[o], bpcs[q]};
+                float ms = 0.f;
+                for (int rep = 0; rep < 2 && st == PCT_OK; ++rep) {
+                    if (hipEventRecord(e0, s) != hipSuccess) st = PCT_EHIP;
+                    if (st == PCT_OK) st = pct_emit_csr(n_jobs, jobs, ws, ws_bytes, stream);
+                    if (st == PCT_OK && hipEventRecord(e1, s) != hipSuccess) st = PCT_EHIP;
+                    if (st == PCT_OK && hipEventSynchronize(e1) != hipSuccess) st = PCT_EHIP;
+                    if (st == PCT_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = PCT_EHIP;
+                }
+                if (st == PCT_OK && (best_ms < 0.f || ms < best_ms)) {
+                    best_ms = ms;
+                    pick = g_cfg;
+                }
             }
         }
     }
@@ -1023,8 +1233,31 @@ pct_status pct_autotune(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws
     (void)hipEventDestroy(e1);
     g_cfg = (st == PCT_OK) ? pick : saved;
     if (st == PCT_OK) st = pct_emit_csr(n_jobs, jobs, ws, ws_bytes, stream);   // final outputs
+    if (st == PCT_OK && keyed) tune_store(key, g_cfg);
     *best = g_cfg;
     return st;
+}
+
+pct_status pct_autotune_cached(int32_t n_jobs, const pct_job *jobs, pct_launch_config *cfg, int32_t *found) {
+    if (!cfg || !found) return PCT_EINVAL;
+    *found = 0;
+    const pct_status st = check_jobs(n_jobs, jobs, false, false);
+    if (st != PCT_OK) return st;
+    uint64_t key = 0;
+    if (!tune_key(n_jobs, jobs, key)) return PCT_EHIP;
+    pct_launch_config c;
+    if (tune_lookup(key, c)) {
+        *cfg = c;
+        *found = 1;
+    }
+    return PCT_OK;
+}
+
+pct_status pct_autotune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    g_tune.map.clear();
+    g_tune.loaded = true;   // the file, if any, is not read again
+    return PCT_OK;
 }
 
 }  // extern "C"
@@ -1036,20 +1269,31 @@ struct pct_graph_s {
 
 extern "C" {
 
-pct_status pct_graph_create(int32_t n_jobs, const pct_job *jobs, int32_t build_x, void *ws, size_t ws_bytes,
-                            int64_t *nnz_total_dev, pct_graph *graph) {
+pct_status pct_graph_create_sets(int32_t n_sets, const int32_t *set_sizes, const pct_job *jobs, int32_t build_x,
+                                 void *ws, size_t ws_bytes, int64_t *nnz_total_dev, pct_graph *graph) {
     if (!graph) return PCT_EINVAL;
     *graph = nullptr;
-    pct_status st = check_jobs(n_jobs, jobs, true, false);
-    if (st != PCT_OK) return st;
-    if (n_jobs > 0 && !nnz_total_dev) return PCT_EINVAL;
+    if (n_sets < 1 || !set_sizes) return PCT_EINVAL;
+    int64_t total = 0;
+    for (int k = 0; k < n_sets; ++k) {
+        if (set_sizes[k] < 0) return PCT_EINVAL;
+        total += set_sizes[k];
+    }
+    if (total > INT32_MAX) return PCT_ERANGE;
+    if (total > 0 && (!jobs || !nnz_total_dev)) return PCT_EINVAL;
+    for (int64_t k = 0, off = 0; k < n_sets; off += set_sizes[k], ++k) {
+        const pct_status st = check_jobs(set_sizes[k], jobs + off, true, false);
+        if (st != PCT_OK) return st;
+    }
     if (build_x) {
-        for (int j = 0; j < n_jobs; ++j)
+        for (int64_t j = 0; j < total; ++j)
             if (!jobs[j].x_dev) return PCT_EINVAL;
     }
     // The count pass does not read x, so the phantom builds form a branch of their own
     // (stream s2, forked from and joined back into the capture stream s) that runs beside
-    // the count pass; the emit, which gathers x, waits for both.
+    // the first set's count pass; its emit, which gathers x, waits for both.  The sets
+    // follow one another on s: count, then emit, each into its own slice of nnz_total_dev.
+    pct_status st = PCT_OK;
     hipStream_t s = nullptr, s2 = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
@@ -1061,18 +1305,20 @@ pct_status pct_graph_create(int32_t n_jobs, const pct_job *jobs, int32_t build_x
     if (st == PCT_OK && build_x) {
         if (hipEventRecord(fork, s) != hipSuccess || hipStreamWaitEvent(s2, fork, 0) != hipSuccess) st = PCT_EHIP;
         std::vector<const float *> done;
-        for (int j = 0; j < n_jobs && st == PCT_OK; ++j) {
+        for (int64_t j = 0; j < total && st == PCT_OK; ++j) {
             const float *x = jobs[j].x_dev;
             if (std::find(done.begin(), done.end(), x) != done.end()) continue;
             done.push_back(x);
             st = pct_phantom_build(jobs[j].phantom, const_cast<float *>(x), s2);
         }
     }
-    if (st == PCT_OK) st = pct_count_rows(n_jobs, jobs, ws, ws_bytes, nnz_total_dev, s);
-    if (st == PCT_OK && build_x) {
-        if (hipEventRecord(join, s2) != hipSuccess || hipStreamWaitEvent(s, join, 0) != hipSuccess) st = PCT_EHIP;
+    for (int64_t k = 0, off = 0; k < n_sets && st == PCT_OK; off += set_sizes[k], ++k) {
+        st = count_common(set_sizes[k], jobs + off, ws, ws_bytes, nnz_total_dev + off, s, k == 0);
+        if (st == PCT_OK && build_x && k == 0) {
+            if (hipEventRecord(join, s2) != hipSuccess || hipStreamWaitEvent(s, join, 0) != hipSuccess) st = PCT_EHIP;
+        }
+        if (st == PCT_OK) st = pct_emit_csr(set_sizes[k], jobs + off, ws, ws_bytes, s);
     }
-    if (st == PCT_OK) st = pct_emit_csr(n_jobs, jobs, ws, ws_bytes, s);
     hipGraph_t g = nullptr;
     const hipError_t ec = capturing ? hipStreamEndCapture(s, &g) : hipSuccess;
     if (join) (void)hipEventDestroy(join);
@@ -1094,6 +1340,12 @@ pct_status pct_graph_create(int32_t n_jobs, const pct_job *jobs, int32_t build_x
     h->exec = e;
     *graph = h;
     return PCT_OK;
+}
+
+pct_status pct_graph_create(int32_t n_jobs, const pct_job *jobs, int32_t build_x, void *ws, size_t ws_bytes,
+                            int64_t *nnz_total_dev, pct_graph *graph) {
+    if (n_jobs < 0) return PCT_EINVAL;
+    return pct_graph_create_sets(1, &n_jobs, jobs, build_x, ws, ws_bytes, nnz_total_dev, graph);
 }
 
 pct_status pct_graph_launch(pct_graph graph, void *stream) {

@@ -36,7 +36,8 @@ SCATTER = {"fixed": PCT_SCATTER_FIXED, "highland": PCT_SCATTER_HIGHLAND}
 SYMBOLS = ("pct_status_string", "pct_version", "pct_phantom_build", "pct_workspace_bytes",
            "pct_count_rows", "pct_emit_csr", "pct_wepl", "pct_device_status", "pct_set_launch_config",
            "pct_get_launch_config", "pct_autotune", "pct_graph_create", "pct_graph_launch", "pct_graph_destroy",
-           "pct_sap_workspace_bytes", "pct_sap_prepare", "pct_sap_iterate", "pct_csr_write", "pct_wepl_static")
+           "pct_sap_workspace_bytes", "pct_sap_prepare", "pct_sap_iterate", "pct_csr_write", "pct_wepl_static",
+           "pct_autotune_cached", "pct_autotune_cache_clear", "pct_graph_create_sets")
 
 
 class PctError(RuntimeError):
@@ -85,7 +86,7 @@ class SapParams(C.Structure):
 
 
 class LaunchConfig(C.Structure):
-    _fields_ = [("rows_per_wave", C.c_int32), ("order", C.c_int32)]
+    _fields_ = [("rows_per_wave", C.c_int32), ("order", C.c_int32), ("blocks_per_cu", C.c_int32)]
 
 
 _lib = None
@@ -121,9 +122,16 @@ def lib():
         L.pct_autotune.argtypes = [C.c_int32, C.POINTER(Job), C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                    C.POINTER(LaunchConfig)]
         L.pct_autotune.restype = C.c_int32
+        L.pct_autotune_cached.argtypes = [C.c_int32, C.POINTER(Job), C.POINTER(LaunchConfig), C.POINTER(C.c_int32)]
+        L.pct_autotune_cached.restype = C.c_int32
+        L.pct_autotune_cache_clear.argtypes = []
+        L.pct_autotune_cache_clear.restype = C.c_int32
         L.pct_graph_create.argtypes = [C.c_int32, C.POINTER(Job), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                        C.POINTER(C.c_void_p)]
         L.pct_graph_create.restype = C.c_int32
+        L.pct_graph_create_sets.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(Job), C.c_int32, C.c_void_p,
+                                            C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.pct_graph_create_sets.restype = C.c_int32
         L.pct_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
         L.pct_graph_launch.restype = C.c_int32
         L.pct_graph_destroy.argtypes = [C.c_void_p]
@@ -300,43 +308,79 @@ def device_status(ws: torch.Tensor, stream=None) -> int:
 ORDERS = {"given": PCT_ORDER_GIVEN, "lpt": PCT_ORDER_LPT}
 
 
-def set_launch_config(rows_per_wave: int | None = None, order: str | None = None):
-    """pct_set_launch_config; no arguments resets the default."""
-    if rows_per_wave is None and order is None:
+def set_launch_config(rows_per_wave: int | None = None, order: str | None = None, blocks_per_cu: int | None = None):
+    """pct_set_launch_config; no arguments resets the default.  blocks_per_cu: 0 for a
+    grid over the emit tiles, 1-8 for a persistent grid taking them from a queue."""
+    if rows_per_wave is None and order is None and blocks_per_cu is None:
         _check(lib().pct_set_launch_config(None), "pct_set_launch_config")
         return
     cur = get_launch_config()
     c = LaunchConfig(int(rows_per_wave if rows_per_wave is not None else cur["rows_per_wave"]),
-                     ORDERS[order] if order is not None else ORDERS[cur["order"]])
+                     ORDERS[order] if order is not None else ORDERS[cur["order"]],
+                     int(blocks_per_cu if blocks_per_cu is not None else cur["blocks_per_cu"]))
     _check(lib().pct_set_launch_config(C.byref(c)), "pct_set_launch_config")
+
+
+def _cfg_dict(c: LaunchConfig) -> dict:
+    inv = {v: k for k, v in ORDERS.items()}
+    return {"rows_per_wave": int(c.rows_per_wave), "order": inv[int(c.order)], "blocks_per_cu": int(c.blocks_per_cu)}
 
 
 def get_launch_config() -> dict:
     c = LaunchConfig()
     _check(lib().pct_get_launch_config(C.byref(c)), "pct_get_launch_config")
-    inv = {v: k for k, v in ORDERS.items()}
-    return {"rows_per_wave": int(c.rows_per_wave), "order": inv[int(c.order)]}
+    return _cfg_dict(c)
 
 
 def autotune(jobs: JobSet, ws: torch.Tensor, nnz_total: torch.Tensor, stream=None) -> dict:
-    """pct_autotune: picks (and sets) the fastest launch configuration for these jobs."""
+    """pct_autotune: picks (and sets) the fastest launch configuration for these jobs, or
+    the cached one for their shape."""
     n, arr = jobs.array()
     c = LaunchConfig()
     _check(lib().pct_autotune(n, arr, _ptr(ws), ws.numel(), _ptr(nnz_total), _stream_ptr(stream), C.byref(c)),
            "pct_autotune")
-    inv = {v: k for k, v in ORDERS.items()}
-    return {"rows_per_wave": int(c.rows_per_wave), "order": inv[int(c.order)]}
+    return _cfg_dict(c)
+
+
+def autotune_cached(jobs: JobSet) -> dict | None:
+    """pct_autotune_cached: the cached configuration for these jobs' shape, or None."""
+    n, arr = jobs.array()
+    c = LaunchConfig()
+    found = C.c_int32(0)
+    _check(lib().pct_autotune_cached(n, arr, C.byref(c), C.byref(found)), "pct_autotune_cached")
+    return _cfg_dict(c) if found.value else None
+
+
+def autotune_cache_clear():
+    _check(lib().pct_autotune_cache_clear(), "pct_autotune_cache_clear")
 
 
 class Graph:
-    """pct_graph_create / pct_graph_launch / pct_graph_destroy for one job set."""
+    """pct_graph_create / pct_graph_launch / pct_graph_destroy for one job set, or
+    pct_graph_create_sets for a list of job sets run one after another (nnz_total then
+    holds every set's jobs back to back)."""
 
-    def __init__(self, jobs: JobSet, ws: torch.Tensor, nnz_total: torch.Tensor, build_x: bool = True):
+    def __init__(self, jobs, ws: torch.Tensor, nnz_total: torch.Tensor, build_x: bool = True):
         self._jobs, self._ws, self._nnz = jobs, ws, nnz_total   # the graph refers to their memory
-        n, arr = jobs.array()
         h = C.c_void_p()
-        _check(lib().pct_graph_create(n, arr, 1 if build_x else 0, _ptr(ws), ws.numel(), _ptr(nnz_total),
-                                      C.byref(h)), "pct_graph_create")
+        if isinstance(jobs, JobSet):
+            n, arr = jobs.array()
+            _check(lib().pct_graph_create(n, arr, 1 if build_x else 0, _ptr(ws), ws.numel(), _ptr(nnz_total),
+                                          C.byref(h)), "pct_graph_create")
+        else:
+            arrays = [js.array() for js in jobs]
+            sizes = (C.c_int32 * len(arrays))(*[n for n, _ in arrays])
+            total = sum(n for n, _ in arrays)
+            assert nnz_total.numel() >= total
+            flat = (Job * max(total, 1))()
+            k = 0
+            for n, arr in arrays:
+                for i in range(n):
+                    flat[k] = arr[i]
+                    k += 1
+            self._flat = flat
+            _check(lib().pct_graph_create_sets(len(arrays), sizes, flat, 1 if build_x else 0, _ptr(ws), ws.numel(),
+                                               _ptr(nnz_total), C.byref(h)), "pct_graph_create_sets")
         self._h = h
 
     def launch(self, stream=None):

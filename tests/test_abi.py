@@ -253,20 +253,22 @@ def test_launch_config_host_side(P):
     assert lib.pct_get_launch_config(None) == -1
     for rpw in (16, 32, 64):
         for order in (P.PCT_ORDER_GIVEN, P.PCT_ORDER_LPT):
-            assert lib.pct_set_launch_config(C.byref(P.LaunchConfig(rpw, order))) == 0
-            got = P.LaunchConfig()
-            lib.pct_get_launch_config(C.byref(got))
-            assert (got.rows_per_wave, got.order) == (rpw, order)
+            for bpc in (0, 1, 4, 8):
+                assert lib.pct_set_launch_config(C.byref(P.LaunchConfig(rpw, order, bpc))) == 0
+                got = P.LaunchConfig()
+                lib.pct_get_launch_config(C.byref(got))
+                assert (got.rows_per_wave, got.order, got.blocks_per_cu) == (rpw, order, bpc)
     before = P.LaunchConfig()
     lib.pct_get_launch_config(C.byref(before))
-    for bad in ((0, 1), (48, 1), (128, 0), (64, 2), (64, -1)):
+    for bad in ((0, 1, 0), (48, 1, 0), (128, 0, 0), (64, 2, 0), (64, -1, 0), (64, 1, -1), (64, 1, 9)):
         assert lib.pct_set_launch_config(C.byref(P.LaunchConfig(*bad))) == -1
         now = P.LaunchConfig()
         lib.pct_get_launch_config(C.byref(now))
-        assert (now.rows_per_wave, now.order) == (before.rows_per_wave, before.order)
+        assert (now.rows_per_wave, now.order, now.blocks_per_cu) == \
+            (before.rows_per_wave, before.order, before.blocks_per_cu)
     assert lib.pct_set_launch_config(None) == 0
     lib.pct_get_launch_config(C.byref(cfg))
-    assert (cfg.rows_per_wave, cfg.order) == (64, P.PCT_ORDER_LPT)
+    assert (cfg.rows_per_wave, cfg.order, cfg.blocks_per_cu) == (64, P.PCT_ORDER_LPT, 0)
 
 
 def test_graph_and_autotune_validate_on_host(P, W):
