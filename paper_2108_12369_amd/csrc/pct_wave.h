@@ -680,50 +680,67 @@ struct Walker {
 };
 
 // Item with at most one crossing per axis.  The displacement and the distance to the
-// face are taken in R from the positions in the voxel (no cancellation for an item
-// nearly parallel to a face), their ratio -- the crossing's parameter in the item --
-// and the piece lengths in FP32.
-template <typename R, int DIM, class F>
+// face are taken in R from the positions in the voxel (no cancellation for an item nearly
+// parallel to a face); their ratio -- the crossing's parameter in the item -- and the
+// piece lengths are FP32.  The crossings are ordered by parameter, ties
+// keeping the lower axis.  The item closes up to DIM entries, staged at the lane's next
+// slots (Pc + done ...); a close with no crossing behind it writes the lane's next slot
+// instead, which a later store of the wave overwrites in program order (this lane's next
+// entry, the head of the next lane with a crossing, or the row's last entry), so every
+// lane stores on every item without a branch.
+template <typename R, int DIM, typename TW>
 __device__ __forceinline__ void item_fast(const float hf[3], const int32_t stride[3], const int Ip[3],
                                           const R Fp[3], const R frp[3], const int Ie[3], const R Fe[3],
-                                          Walker &wk, F &&close) {
+                                          Walker &wk, RowOut<TW> &out, int Pc) {
     float lam[3] = {2.f, 2.f, 2.f}, dn2 = 0.f;
-    int32_t dcol[3] = {0, 0, 0};
+    int32_t dc[3] = {0, 0, 0};
     int tot = 0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        const int di = Ie[d] - Ip[d];
+        const int di = Ie[d] - Ip[d];   // -1, 0 or 1
         const float dff = (float)(Fe[d] - Fp[d]);
         const float dm = dff * hf[d];
         dn2 = fmaf(dm, dm, dn2);
-        const bool up = di > 0;
-        const float dist = (float)(frp[d] - (up ? R(1) : R(0)));   // minus the distance when up
-        lam[d] = di != 0 ? fabsf(dist) * __builtin_amdgcn_rcpf(fabsf(dff)) : 2.f;
-        dcol[d] = up ? stride[d] : -stride[d];
+        // distance to the face crossed, in R and rounded once: near a face its absolute
+        // error must stay small, since a chord nearly parallel to the face divides it by a
+        // small displacement
+        const float dist = (float)(frp[d] - (di > 0 ? R(1) : R(0)));
+        // in [0, 1] (a NaN from a vanishing displacement becomes 1: the item's end)
+        lam[d] = di != 0 ? fminf(fabsf(dist) * __builtin_amdgcn_rcpf(fabsf(dff)), 1.f) : 2.f;
+        dc[d] = di * stride[d];
         tot += di != 0 ? 1 : 0;
     }
     const float len = __builtin_amdgcn_sqrtf(dn2);
-    // order the crossings; ties keep the lower axis
-#define PCT_CSWAP(a, b)                                                  \
-    if (lam[b] < lam[a]) {                                               \
-        const float tl = lam[a]; lam[a] = lam[b]; lam[b] = tl;           \
-        const int32_t tc = dcol[a]; dcol[a] = dcol[b]; dcol[b] = tc;     \
-    }
-    PCT_CSWAP(0, 1)
+    // parameters in order, and the column steps of the first and the last crossing axis
+    float l0, l1, l2 = 2.f;
+    int32_t dfirst, dlast;
     if (DIM == 3) {
-        PCT_CSWAP(1, 2)
-        PCT_CSWAP(0, 1)
+        const bool c10 = lam[1] < lam[0], c20 = lam[2] < lam[0], c21 = lam[2] < lam[1];
+        l0 = fminf(fminf(lam[0], lam[1]), lam[2]);
+        l1 = __builtin_amdgcn_fmed3f(lam[0], lam[1], lam[2]);
+        l2 = fmaxf(fmaxf(lam[0], lam[1]), lam[2]);
+        dfirst = (!c10 && !c20) ? dc[0] : ((c10 && !c21) ? dc[1] : dc[2]);
+        dlast = (c10 && c20) ? dc[0] : ((!c10 && c21) ? dc[1] : dc[2]);
+    } else {
+        const bool c10 = lam[1] < lam[0];
+        l0 = fminf(lam[0], lam[1]);
+        l1 = fmaxf(lam[0], lam[1]);
+        dfirst = c10 ? dc[1] : dc[0];
+        dlast = c10 ? dc[0] : dc[1];
     }
-#undef PCT_CSWAP
-    float lp = 0.f;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        const bool go = k < tot;
-        const float lc = fminf(fmaxf(lam[k], lp), 1.f);   // lam is never NaN
-        close(k, go, wk.cur, k == 0 ? wk.pend + (lc - lp) * len : (lc - lp) * len);
-        wk.cur += go ? dcol[k] : 0;
-        lp = go ? lc : lp;
-    }
+    const int32_t dsum = DIM == 3 ? dc[0] + dc[1] + dc[2] : dc[0] + dc[1];
+    const int base = wk.done, slot = Pc + base;
+    // first crossing: closes the entry open at the item's start
+    const float len0 = fmaf(l0, len, wk.pend);
+    wk.head = (base == 0 && tot > 0) ? len0 : wk.head;   // the lane's first entry
+    out.put(slot, wk.cur, len0);
+    const int32_t cur1 = wk.cur + dfirst;
+    out.put(slot + (tot < 1 ? tot : 1), cur1, (l1 - l0) * len);   // second crossing
+    if (DIM == 3)   // third crossing
+        out.put(slot + (tot < 2 ? tot : 2), cur1 + dsum - dfirst - dlast, (l2 - l1) * len);
+    const float lp = DIM == 3 && tot > 2 ? l2 : (tot > 1 ? l1 : (tot > 0 ? l0 : 0.f));
+    wk.cur += dsum;
+    wk.done = base + tot;
     wk.pend = (tot == 0 ? wk.pend : 0.f) + (1.f - lp) * len;
 }
 
@@ -966,7 +983,7 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, Lds
             } else {
                 piece_next<R, DIM>(P, m, mf, Fe);
                 piece_voxel<R, DIM>(P, Fe, Ie, fre);
-                if (FAST) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
+                if (FAST) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, out, Pc);
                 else item_general<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
             }
 #pragma unroll
