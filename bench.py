@@ -192,10 +192,12 @@ class Pipeline:
         return self.bytes_emit() + 4 * nvox + self.total_rows * (4 * 3 + 8)
 
 
-def stored_traffic(kernel, workload_name):
+def stored_traffic(kernel, workload_name, key="traffic_bytes_per_launch"):
     """HBM bytes per launch of `kernel` on this workload from the committed profile
     summaries (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when
-    no summary exists or the kernels have changed since it was taken."""
+    no summary exists or the kernels have changed since it was taken.  key
+    "valu_issue_frac": the emit kernels' VALU wave instructions per second over the
+    chip's issue rate (one per CU per clock), from the same summary's counters."""
     from paper_2108_12369_amd import build as B
     digest = B.source_digest()
     pdir = os.path.join(ROOT, "profiles")
@@ -211,8 +213,8 @@ def stored_traffic(kernel, workload_name):
                     k, v = line[2:].split(":", 1)
                     kv[k.strip()] = v.strip()
         if kv.get("kernel") == kernel and kv.get("workload") == workload_name \
-                and kv.get("source_digest") == digest and "traffic_bytes_per_launch" in kv:
-            return float(kv["traffic_bytes_per_launch"])
+                and kv.get("source_digest") == digest and key in kv:
+            return float(kv[key])
     return None
 
 
@@ -594,6 +596,7 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": stored_traffic("k_emit_wave", wname),
+                     "valu_issue_frac": stored_traffic("k_emit_wave", wname, "valu_issue_frac"),
                      "emit_ms_per_launch": emit_launch_ms, "algorithmic_bytes_per_launch": emit_bytes_launch},
     }
     if args.workload == "c3" and "plain_single" in bt:
@@ -623,6 +626,7 @@ def main():
                            ("c4", min(args.steps, 2), 1)):
             legs[name] = workload_leg(P, W, name, k, w, not args.no_tune, plain=not args.no_plain)
             legs[name]["roofline_traffic"] = stored_traffic("k_emit_wave", legs[name]["workload"])
+            legs[name]["valu_issue_frac"] = stored_traffic("k_emit_wave", legs[name]["workload"], "valu_issue_frac")
         res["legs"] = legs
 
     if not args.no_options:
