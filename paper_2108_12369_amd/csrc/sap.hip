@@ -30,6 +30,9 @@
 // slots; the two waves meet at a workgroup barrier once per row.  A row whose columns
 // are distinct (the prepare pass marks the others) is written back with plain stores,
 // which stay in the XCD's L2 for the next row's gathers; global atomic adds would not.
+// The staged entries' gathers and stores go through a buffer resource over y: an entry
+// past the row gets an offset outside it (the load returns 0, the store is dropped), so
+// each chunk is one instruction with no branch around it.
 #include "../../include/pct.h"
 #include "pct_device.h"
 #include "pct_wave.h"
@@ -441,6 +444,20 @@ __global__ __launch_bounds__(64) void k_sap_string(SapArgs a, const float *x, fl
     for (int j = lane; j < n; j += 64) yg[j] = ys[j];
 }
 
+// Buffer access to a string's y (n binary32): an offset at or past 4 n bytes is outside
+// the resource (n < 2^29, checked on the host, so Y_OUT always is).  Cache policy as the
+// workgroup-scope accesses above.
+constexpr uint32_t Y_OUT = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t y_rsrc(float *y, int32_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(y, (short)0, n * 4, 0x00020000);
+}
+__device__ __forceinline__ float yb_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 1));
+}
+__device__ __forceinline__ void yb_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 1);
+}
+
 // Barrier between the two waves of k_sap_string_ws: their LDS accesses before it happen
 // before those after it (lgkmcnt(0), s_barrier); global loads stay in flight.
 __device__ __forceinline__ void lds_barrier() {
@@ -514,6 +531,7 @@ __global__ __launch_bounds__(128) void k_sap_string_ws(SapArgs a, const float *x
     } else {
         // projector
         const uint32_t nu = (uint32_t)n;
+        const __amdgpu_buffer_rsrc_t yr = y_rsrc(y, n);
         for (int64_t k = 0; k < steps; ++k) {
             if (k > 0) {
                 const int slot = (int)((k - 1) & 1);
@@ -532,7 +550,7 @@ __global__ __launch_bounds__(128) void k_sap_string_ws(SapArgs a, const float *x
                         ok[q] = beg + q * 64 + lane < end && (uint32_t)cc[q] < nu;
                     }
 #pragma unroll
-                    for (int q = 0; q < PF; ++q) yv[q] = ok[q] ? ws_load(y, cc[q]) : 0.0f;
+                    for (int q = 0; q < PF; ++q) yv[q] = yb_load(yr, ok[q] ? (uint32_t)cc[q] * 4u : Y_OUT);
                     double acc = 0.0;
 #pragma unroll
                     for (int q = 0; q < PF; ++q) acc = fma(ok[q] ? (double)cv[q] : 0.0, (double)yv[q], acc);
@@ -555,7 +573,7 @@ __global__ __launch_bounds__(128) void k_sap_string_ws(SapArgs a, const float *x
                     } else {
 #pragma unroll
                         for (int q = 0; q < PF; ++q)
-                            if (ok[q]) ws_put(y, cc[q], yv[q] + alpha * cv[q]);
+                            yb_store(yr, ok[q] ? (uint32_t)cc[q] * 4u : Y_OUT, yv[q] + alpha * cv[q]);
                         for (int64_t e = beg + SLOT + lane; e < end; e += 64) {
                             const int32_t c = a.cols[e];
                             if ((uint32_t)c < nu) ws_put(y, c, ws_load(y, c) + alpha * val_at<VT>(a.vals, e));
@@ -607,6 +625,7 @@ pct_status check_sap(const pct_csr *A, const pct_sap *p) {
     // (t + 1) * m must not overflow int64; the string iterates must be addressable
     if ((double)A->n_rows * (double)p->n_strings > 9.0e18) return PCT_ERANGE;
     if ((double)p->n_strings * (double)A->n_cols * 4.0 > 4.0e18) return PCT_ERANGE;
+    if (A->n_cols >= (1 << 29)) return PCT_ERANGE;   // byte offsets into one string's y
     return PCT_OK;
 }
 

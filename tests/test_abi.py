@@ -303,7 +303,7 @@ def test_sap_validation_on_host(P):
     need = L.pct_sap_workspace_bytes(C.byref(A), C.byref(p))
     # header + 10 coefficients + 3 weights + 3 x 5 string iterates, 256-byte aligned parts
     assert need == 256 + 256 + 256 + 3 * 5 * 4
-    for field, bad in (("n_cols", 0), ("n_rows", -1), ("val_dtype", 7), ("nnz", -1)):
+    for field, bad in (("n_cols", 0), ("n_cols", 1 << 29), ("n_rows", -1), ("val_dtype", 7), ("nnz", -1)):
         B = P.Csr.from_buffer_copy(A)
         setattr(B, field, bad)
         assert L.pct_sap_workspace_bytes(C.byref(B), C.byref(p)) == 0, field

@@ -190,6 +190,56 @@ def test_sap_lds_rows_of_every_length(P, oracle, val_dtype):
     _close(got, _oracle_sap(oracle, sd, x0, 1, n_strings=33, relax=1.3, order=order), 1e-5)
 
 
+def _chain_system(seed, n, m, vdt):
+    """Synthetic rows whose columns lie in a window that drifts by less than a row's
+    length, so most consecutive rows share hundreds of columns: lengths 0 to 3,000
+    (around the 768 entries the workspace iterate stages and the 2,048 above which a row
+    waits for its own stores), some rows empty, some repeating a column."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(size=m)
+    lens = np.where(u < 0.6, rng.integers(1, 769, m),
+                    np.where(u < 0.85, rng.integers(769, 2049, m), rng.integers(2049, 3001, m)))
+    lens[rng.uniform(size=m) < 0.08] = 0
+    lens[:10] = [1, 767, 768, 769, 0, 2047, 2048, 2049, 3000, 5]
+    cols, center = [], n // 2
+    for L in (int(v) for v in lens):
+        if L == 0:
+            continue
+        w = max(L, int(L * rng.uniform(1.0, 2.0)))
+        start = min(max(center - w // 2, 0), n - w)
+        cols.append(start + rng.choice(w, L, replace=False))
+        center = int(min(max(center + rng.integers(-(L // 4) - 1, L // 4 + 2), 0), n - 1))
+    rp = np.zeros(m + 1, np.int64)
+    rp[1:] = np.cumsum(lens)
+    cols = np.concatenate(cols).astype(np.int32)
+    rep = rng.choice(np.nonzero(lens >= 2)[0], m // 12, replace=False)
+    cols[rp[rep + 1] - 1] = cols[rp[rep]]   # the last entry repeats the first column
+    vals = rng.uniform(0.05, 2.0, int(rp[-1])).astype(np.float32).astype(vdt)
+    rows = np.repeat(np.arange(m), lens)
+    b = np.bincount(rows, vals.astype(np.float64) * rng.uniform(0.0, 1.5, n)[cols], minlength=m)
+    b[lens == 0] = 1.0
+    return dict(row_ptr=rp, cols=cols, vals=vals, b=b.astype(np.float32), n=n), rng.uniform(0.0, 1.5, n)
+
+
+@pytest.mark.parametrize("val_dtype", ["f16", "f32"])
+def test_sap_workspace_consecutive_rows_share_columns(P, oracle, val_dtype):
+    """y in the workspace (n = 50,000) and consecutive rows that share columns: a row's
+    gathers are issued while the previous row's stores to the same columns may still be
+    in flight, and must see those stores' values.  Rows that repeat a column, rows too
+    long for the table of writes in flight and empty rows sit between them.  A row that
+    missed the previous row's writes would move the result by a few percent; the FP32
+    iterate stays within 1e-6 of max|x| of the binary64 oracle here."""
+    sd, x0 = _chain_system(81 if val_dtype == "f16" else 82, 50000, 600,
+                           np.float16 if val_dtype == "f16" else np.float32)
+    assert sd["n"] * 4 > 160 * 1024
+    lens = np.diff(sd["row_ptr"])
+    assert (lens > 2048).sum() > 20 and (lens == 0).sum() > 20
+    for M, relax, it in ((1, 0.8, 2), (4, 1.3, 1)):
+        got, st = _gpu_sap(P, sd, x0, it, n_strings=M, relax=relax)
+        assert st == 0
+        _close(got, _oracle_sap(oracle, sd, x0, it, n_strings=M, relax=relax), 1e-5)
+
+
 @pytest.mark.parametrize("n", [40896, 40897])
 def test_sap_at_the_lds_limit(P, oracle, n):
     """n on both sides of the LDS limit: 4 (n + 64) bytes = 160 KiB at n = 40,896 (the
