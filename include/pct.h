@@ -297,7 +297,7 @@ pct_status pct_graph_destroy(pct_graph graph);
  * weighted sum over strings in binary64 in string order (deterministic). */
 typedef struct {
     int64_t n_rows;               /* m >= 0 */
-    int32_t n_cols;               /* n >= 1, the length of x */
+    int32_t n_cols;               /* 1 <= n < 2^29, the length of x */
     int32_t val_dtype;            /* PCT_F32 | PCT_F16 */
     int64_t nnz;                  /* length of cols_dev and vals_dev */
     const int64_t *row_ptr_dev;   /* m + 1 entries, non-decreasing, within [0, nnz] */

@@ -680,9 +680,10 @@ struct Walker {
 };
 
 // Item with at most one crossing per axis.  The displacement and the distance to the
-// face are taken in R from the positions in the voxel (no cancellation for an item nearly
-// parallel to a face); their ratio -- the crossing's parameter in the item -- and the
-// piece lengths are FP32.  The crossings are ordered by parameter, ties
+// face are taken in R from the positions (no cancellation for an item nearly parallel to
+// a face); their ratio -- the crossing's parameter in the item -- and the piece lengths
+// are FP32.  The face distance F - (I + 1) or F - I equals the position in the voxel
+// (F - I, exact) less 1 or 0, bit for bit.  The crossings are ordered by parameter, ties
 // keeping the lower axis.  The item closes up to DIM entries, staged at the lane's next
 // slots (Pc + done ...); a close with no crossing behind it writes the lane's next slot
 // instead, which a later store of the wave overwrites in program order (this lane's next
@@ -690,8 +691,8 @@ struct Walker {
 // lane stores on every item without a branch.
 template <typename R, int DIM, typename TW>
 __device__ __forceinline__ void item_fast(const float hf[3], const int32_t stride[3], const int Ip[3],
-                                          const R Fp[3], const R frp[3], const int Ie[3], const R Fe[3],
-                                          Walker &wk, RowOut<TW> &out, int Pc) {
+                                          const R Fp[3], const int Ie[3], const R Fe[3], Walker &wk,
+                                          RowOut<TW> &out, int Pc) {
     float lam[3] = {2.f, 2.f, 2.f}, dn2 = 0.f;
     int32_t dc[3] = {0, 0, 0};
     int tot = 0;
@@ -704,7 +705,7 @@ __device__ __forceinline__ void item_fast(const float hf[3], const int32_t strid
         // distance to the face crossed, in R and rounded once: near a face its absolute
         // error must stay small, since a chord nearly parallel to the face divides it by a
         // small displacement
-        const float dist = (float)(frp[d] - (di > 0 ? R(1) : R(0)));
+        const float dist = (float)(Fp[d] - R(Ip[d] + (di > 0 ? 1 : 0)));
         // in [0, 1] (a NaN from a vanishing displacement becomes 1: the item's end)
         lam[d] = di != 0 ? fminf(fabsf(dist) * __builtin_amdgcn_rcpf(fabsf(dff)), 1.f) : 2.f;
         dc[d] = di * stride[d];
@@ -722,9 +723,10 @@ __device__ __forceinline__ void item_fast(const float hf[3], const int32_t strid
         dfirst = (!c10 && !c20) ? dc[0] : ((c10 && !c21) ? dc[1] : dc[2]);
         dlast = (c10 && c20) ? dc[0] : ((!c10 && c21) ? dc[1] : dc[2]);
     } else {
+        // (the parameters are never NaN: a select is the minimum and the maximum)
         const bool c10 = lam[1] < lam[0];
-        l0 = fminf(lam[0], lam[1]);
-        l1 = fmaxf(lam[0], lam[1]);
+        l0 = c10 ? lam[1] : lam[0];
+        l1 = c10 ? lam[0] : lam[1];
         dfirst = c10 ? dc[1] : dc[0];
         dlast = c10 ? dc[0] : dc[1];
     }
@@ -983,7 +985,7 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, Lds
             } else {
                 piece_next<R, DIM>(P, m, mf, Fe);
                 piece_voxel<R, DIM>(P, Fe, Ie, fre);
-                if (FAST) item_fast<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, out, Pc);
+                if (FAST) item_fast<R, DIM>(hf, stride, Ip, Fp, Ie, Fe, wk, out, Pc);
                 else item_general<R, DIM>(hf, stride, Ip, Fp, frp, Ie, Fe, wk, close);
             }
 #pragma unroll
@@ -1104,7 +1106,9 @@ __device__ __forceinline__ void wave_ray_row(const JobDev &J, RowRefD<double, DI
             tc = a2 ? tn2 : tc;
             dc = a2 ? dcol[2] : dc;
         }
-        tc = r_fmax<R>(tc, tprev);
+        // tc >= tprev: each axis' parameters grow with k (an fma with a positive
+        // reciprocal rounds monotonically), the smallest of them never falls below the
+        // last one taken, and the first is at or past ta, which bounds tprev
         out.put(Pc + j, cur, (float)(tc - tprev) * Lt);
         cur += dc;
         tprev = tc;
