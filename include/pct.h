@@ -167,9 +167,13 @@ pct_status pct_phantom_build(const pct_phantom *phantom, float *x_dev, void *str
 
 /* Bytes of device workspace that pct_count_rows / pct_emit_csr / pct_wepl need for
  * these jobs (0 if a descriptor is invalid).  The workspace holds the job table, the
- * per-row counts, the scan partials, a description of every row's path and a status
- * word.  pct_emit_csr reads the path descriptions that pct_count_rows wrote: pass it
- * the same workspace and the same jobs (output pointers may differ). */
+ * per-row counts, the scan partials, a description of every row's path, a status word
+ * and, for each 3D job with n[0] <= 1024 and n[1], n[2] <= 2048, a copy of x in bricks
+ * of 8 x 8 x 1 voxels that pct_emit_csr and pct_wepl refill from x_dev on every call
+ * (the gathers of b read it: a cache line then covers a patch of a plane instead of a
+ * stretch of one grid row).  pct_emit_csr reads the path descriptions that
+ * pct_count_rows wrote: pass it the same workspace and the same jobs (output pointers
+ * may differ). */
 size_t pct_workspace_bytes(int32_t n_jobs, const pct_job *jobs);
 
 /* Count pass: for every row of every job the number of CSR entries the path produces
@@ -200,9 +204,10 @@ pct_status pct_wepl(int32_t n_jobs, const pct_job *jobs, void *ws_dev, size_t ws
  * same kernels and the same b, bit for bit, with the workspace taken from a static
  * device array of 64 MiB per GPU (resolved on the first call on each device and held
  * until the process ends).  The call allocates nothing, on the device or on the host.
- * Limits: at most 64 jobs, and no more rows than pct_workspace_bytes of the jobs fits
- * in 64 MiB (about 180,000 rows); beyond either nothing is enqueued and PCT_ESCRATCH is
- * returned.  status_dev (device int32, nullable) receives the device status word after
+ * Its gathers of b read x_dev itself (no bricked copy of x).  Limits: at most 64 jobs,
+ * and no more rows than the workspace of the jobs without the bricked copies
+ * (pct_workspace_bytes less those) fits in 64 MiB (about 180,000 rows); beyond either
+ * nothing is enqueued and PCT_ESCRATCH is returned.  status_dev (device int32, nullable) receives the device status word after
  * the call (PCT_OK, or PCT_EINTERNAL).  Every call on one GPU uses that GPU's one array:
  * calls that overlap on one GPU (other streams, other host threads) race and must be
  * ordered by the caller. */

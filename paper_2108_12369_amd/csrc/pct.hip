@@ -43,7 +43,7 @@ static_assert(sizeof(WsHeader) == 256, "the header is 256 bytes");
 static inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t jobs_off, order_off, sums_off, offs_off, flags_off, counts_off, rows_off, total;
+    size_t jobs_off, order_off, sums_off, offs_off, flags_off, counts_off, rows_off, bricks_off, total;
     int64_t total_tiles, total_rows;
 };
 
@@ -51,7 +51,17 @@ struct Layout {
 constexpr size_t ROWW_BYTES = rv_bytes<double>() > rv_bytes<float>() ? rv_bytes<double>() : rv_bytes<float>();
 static_assert(TILE == RV_TILE, "descriptions are stored per count tile");
 
-static Layout layout_of(int32_t n_jobs, const int64_t *row_counts) {
+// Bricked copy of x (8 x 8 x 1 voxels per brick) for a 3D job whose voxel coordinates
+// pack into 32 bits (x < 1024, y < 2048, z < 2048) and whose padded grid stays below 2^31
+// voxels: its element count, else 0.
+static int64_t brick_elems(const pct_phantom &ph) {
+    if (ph.dim != 3 || ph.n[0] > 1024 || ph.n[1] > 2048 || ph.n[2] > 2048) return 0;
+    const int64_t e = (int64_t)((ph.n[0] + 7) / 8) * 8 * (int64_t)((ph.n[1] + 7) / 8) * 8 * ph.n[2];
+    return e < ((int64_t)1 << 31) ? e : 0;
+}
+
+// Workspace layout; brick_bytes: per job, the bytes of its bricked copy of x (null: none).
+static Layout layout_of(int32_t n_jobs, const int64_t *row_counts, const size_t *brick_bytes = nullptr) {
     Layout L{};
     int64_t tiles = 0, rows = 0;
     for (int j = 0; j < n_jobs; ++j) {
@@ -67,7 +77,11 @@ static Layout layout_of(int32_t n_jobs, const int64_t *row_counts) {
     L.flags_off = align256(L.offs_off + (size_t)(tiles + 1) * sizeof(int64_t));
     L.counts_off = align256(L.flags_off + (size_t)(tiles + 1) * sizeof(int32_t));
     L.rows_off = align256(L.counts_off + (size_t)rows * sizeof(int32_t));
-    L.total = align256(L.rows_off + (size_t)tiles * RV_TILE * ROWW_BYTES);   // whole tiles of descriptions
+    L.bricks_off = align256(L.rows_off + (size_t)tiles * RV_TILE * ROWW_BYTES);   // whole tiles of descriptions
+    size_t bricks = 0;
+    if (brick_bytes)
+        for (int j = 0; j < n_jobs; ++j) bricks += align256(brick_bytes[j]);
+    L.total = L.bricks_off + bricks;
     return L;
 }
 
@@ -82,6 +96,28 @@ struct JobPack {
 
 // Kernel arguments are copied at launch (and into a graph node at capture), so the
 // job table reaches the device without a host buffer that has to outlive the call.
+// Bricked copy of x for the b gathers of a 3D job (blockIdx.y: the job; jobs without one
+// return at once).  Brick (bx, by, z) holds the voxels x in [8 bx, 8 bx + 8) and y in
+// [8 by, 8 by + 8) of plane z, x fastest; the bricks follow x, then y, then z, so that a
+// 128-byte line covers an 8 x 4 patch of a plane.  Voxels past the grid are 0; no gather
+// index reaches them.  The copy has fewer than 2^31 elements (brick_elems).
+constexpr int BRICK_BLOCKS = 512;
+__global__ void __launch_bounds__(256) k_brick(const JobDev *__restrict__ jobs, int32_t job0) {
+    const JobDev &J = jobs[job0 + (int32_t)blockIdx.y];
+    float *xb = J.xb;
+    if (!xb) return;
+    const uint32_t nbx = (uint32_t)J.nbx, nby = (uint32_t)J.nby, n0 = (uint32_t)J.n[0], n1 = (uint32_t)J.n[1];
+    const uint32_t total = nbx * nby * (uint32_t)J.n[2] * 64u;
+    const float *x = J.x;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const uint32_t brick = e >> 6, r = brick / nbx;
+        const uint32_t ix = (brick - r * nbx) * 8u + (e & 7u);
+        const uint32_t iz = r / nby;
+        const uint32_t iy = (r - iz * nby) * 8u + ((e >> 3) & 7u);
+        xb[e] = (ix < n0 && iy < n1) ? x[(size_t)ix + (size_t)n0 * ((size_t)iy + (size_t)n1 * iz)] : 0.0f;
+    }
+}
+
 __global__ void k_put_jobs(JobDev *dst, JobPack pack) {
     const int words = (int)(sizeof(JobDev) / sizeof(uint64_t)) * pack.count;
     const uint64_t *src = reinterpret_cast<const uint64_t *>(pack.jobs);
@@ -802,24 +838,29 @@ struct HostJobs {
     JobDev jobs_fixed[FIXED];
     int32_t order_fixed[FIXED];
     double cost_fixed[FIXED];
+    size_t bb_fixed[FIXED];
     std::vector<int64_t> rc_heap;
     std::vector<JobDev> jobs_heap;
     std::vector<int32_t> order_heap;
     std::vector<double> cost_heap;
+    std::vector<size_t> bb_heap;
     int64_t *rc = rc_fixed;
     JobDev *jobs = jobs_fixed;
     int32_t *order = order_fixed;
     double *cost = cost_fixed;
+    size_t *bb = bb_fixed;   // bytes of each job's bricked copy of x
     explicit HostJobs(int32_t n) {
         if (n > FIXED) {
             rc_heap.resize(n);
             jobs_heap.resize(n);
             order_heap.resize(n);
             cost_heap.resize(n);
+            bb_heap.resize(n);
             rc = rc_heap.data();
             jobs = jobs_heap.data();
             order = order_heap.data();
             cost = cost_heap.data();
+            bb = bb_heap.data();
         }
     }
     HostJobs(const HostJobs &) = delete;
@@ -832,23 +873,37 @@ struct Prepared {
     pct_launch_config cfg = DEFAULT_CFG;
     int64_t total_etiles = 0;
     int64_t dim_base[2] = {0, 0}, dim_tiles[2] = {0, 0};   // emit tiles of the 2D jobs, then the 3D jobs
+    bool any_bricks = false;                                 // some job has a bricked copy of x to fill
     explicit Prepared(int32_t n) : H(n) {}
 };
 
 // Job table (caller's order; the count pass uses it as is) and the emit launch order,
-// both uploaded through kernel arguments.
+// both uploaded through kernel arguments.  bricks: 3D jobs that allow it get a bricked
+// copy of x in the workspace (every call on a workspace sized by pct_workspace_bytes).
 static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, Prepared &P,
-                          hipStream_t st) {
+                          hipStream_t st, bool bricks = true) {
     int64_t *rc = P.H.rc;
     JobDev *jd = P.H.jobs;
-    for (int j = 0; j < n_jobs; ++j) rc[j] = jobs[j].beam->row_count;
-    P.L = layout_of(n_jobs, rc);
+    size_t *bb = P.H.bb;
+    for (int j = 0; j < n_jobs; ++j) {
+        rc[j] = jobs[j].beam->row_count;
+        bb[j] = bricks ? (size_t)brick_elems(*jobs[j].phantom) * sizeof(float) : 0;
+    }
+    P.L = layout_of(n_jobs, rc, bb);
     if (!ws || ws_bytes < P.L.total) return PCT_EWORKSPACE;
     int64_t count_off = 0, tile_base = 0;
+    size_t boff = P.L.bricks_off;
     for (int j = 0; j < n_jobs; ++j) {
         jd[j] = make_job(jobs[j], count_off, tile_base);
         count_off += rc[j];
         tile_base += jd[j].n_tiles;
+        if (bb[j] > 0 && jobs[j].x_dev) {
+            jd[j].xb = reinterpret_cast<float *>((char *)ws + boff);
+            jd[j].nbx = (jd[j].n[0] + 7) / 8;
+            jd[j].nby = (jd[j].n[1] + 7) / 8;
+            P.any_bricks = true;
+        }
+        boff += align256(bb[j]);
     }
     const pct_launch_config cfg = g_cfg;
     P.cfg = cfg;
@@ -997,8 +1052,12 @@ pct_status pct_phantom_build(const pct_phantom *ph, float *x_dev, void *stream) 
 size_t pct_workspace_bytes(int32_t n_jobs, const pct_job *jobs) {
     if (check_jobs(n_jobs, jobs, false, false) != PCT_OK) return 0;
     std::vector<int64_t> rc(n_jobs > 0 ? n_jobs : 1);
-    for (int j = 0; j < n_jobs; ++j) rc[j] = jobs[j].beam->row_count;
-    return layout_of(n_jobs, rc.data()).total;
+    std::vector<size_t> bb(n_jobs > 0 ? n_jobs : 1);
+    for (int j = 0; j < n_jobs; ++j) {
+        rc[j] = jobs[j].beam->row_count;
+        bb[j] = (size_t)brick_elems(*jobs[j].phantom) * sizeof(float);
+    }
+    return layout_of(n_jobs, rc.data(), bb.data()).total;
 }
 
 }  // extern "C"
@@ -1051,17 +1110,22 @@ static pct_status count_common(int32_t n_jobs, const pct_job *jobs, void *ws, si
 extern "C" {
 
 static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, size_t ws_bytes, void *stream,
-                              bool store) {
+                              bool store, bool bricks = true) {
     pct_status st = check_jobs(n_jobs, jobs, store, !store);
     if (st != PCT_OK) return st;
     if (n_jobs == 0) return PCT_OK;
     hipStream_t s = (hipStream_t)stream;
     if (!ws) return PCT_EWORKSPACE;
     Prepared P(n_jobs);
-    st = prepare(n_jobs, jobs, ws, ws_bytes, P, s);
+    st = prepare(n_jobs, jobs, ws, ws_bytes, P, s, bricks);
     if (st != PCT_OK) return st;
     char *w = (char *)ws;
     const JobDev *J = (const JobDev *)(w + P.L.jobs_off);
+    if (P.any_bricks && P.L.total_tiles > 0)
+        for (int32_t j0 = 0; j0 < n_jobs; j0 += 65535) {
+            const int32_t nj = n_jobs - j0 < 65535 ? n_jobs - j0 : 65535;
+            hipLaunchKernelGGL(k_brick, dim3(BRICK_BLOCKS, (unsigned)nj), dim3(256), 0, s, J, j0);
+        }
     int32_t *status = &((WsHeader *)w)->status;
     // WEPL only runs its own count pass: the status word starts afresh, as in a count call
     if (!store) hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, (WsHeader *)w);
@@ -1151,7 +1215,7 @@ pct_status pct_wepl_static(int32_t n_jobs, const pct_job *jobs, int32_t *status_
     void *ws = nullptr;
     st = static_scratch((hipStream_t)stream, &ws);
     if (st != PCT_OK) return st;
-    st = emit_common(n_jobs, jobs, ws, STATIC_SCRATCH_BYTES, stream, false);
+    st = emit_common(n_jobs, jobs, ws, STATIC_SCRATCH_BYTES, stream, false, false);
     if (st != PCT_OK) return st;
     if (status_dev) {
         // (with no job the status word was not cleared: report OK without reading it)

@@ -62,6 +62,11 @@ struct JobDev {
     double orot[2];      // outer boundary turned by its angle: cosine, sine
     int32_t orot_on;     // the outer boundary is turned
     int32_t pad2_;
+    // 3D jobs: a copy of x in bricks of 8 x 8 x 1 voxels (in the workspace) that the b
+    // gathers of the wave emit read; null when the job has none.  nbx, nby: bricks per
+    // grid row and per plane.
+    float *xb;
+    int32_t nbx, nby;
 };
 
 // ------------------------------------------------------------------ math helpers

@@ -576,12 +576,18 @@ template <typename T> __device__ __forceinline__ T load_uniform(const T *p) {
     return *(const __attribute__((address_space(4))) T *)p;
 }
 
+// Bit offsets of y and z in the packed voxel coordinates of a staged entry (stage_strides).
+constexpr int PACK_Y = 10, PACK_Z = 21;
+
 template <typename TW>
 struct RowOut {
     PCT_GLOBAL int32_t *cols;
     PCT_GLOBAL uint16_t *vh;   // binary16 bits
     PCT_GLOBAL float *vf;
     PCT_GLOBAL const float *x;
+    PCT_GLOBAL const float *xb;   // the bricked copy of x (staged entries hold packed
+    bool pack;                    // coordinates); gn: grid sizes, nbx, nby: bricks per
+    uint32_t gn[3], nbx, nby;     // grid row and per plane
     uint2 *stage;   // the wave's LDS slice
     uint32_t nvox;  // size of x: every gather index is kept below it
     int32_t len;
@@ -620,8 +626,10 @@ struct RowOut {
     // entries (neighbouring voxels along the path share the cache lines of x), in groups
     // of 256 without branches inside a group: all LDS reads, then all gathers (an entry
     // past the row reads x[0], one cache line for all of them, and counts 0), then the
-    // stores, so that each kind of access is in flight together.
-    template <bool WB, bool HALF>
+    // stores, so that each kind of access is in flight together.  With packed coordinates
+    // (PACK) the column and the brick address are computed from them; an entry whose
+    // coordinates lie outside the grid reads element 0 of the copy.
+    template <bool WB, bool HALF, bool PACK>
     __device__ __forceinline__ void flush_t(int n, int lane) {
         constexpr int G = 4;   // chunks of 64 entries per group
         n = n < STAGE_CAP + 1 ? n : STAGE_CAP + 1;
@@ -631,21 +639,37 @@ struct RowOut {
         for (int g0 = 0; g0 < n; g0 += G * WAVE) {
             uint2 v[G];
             float xv[G];
+            uint32_t col[G], xi[G];
 #pragma unroll
             for (int u = 0; u < G; ++u) v[u] = stage[g0 + u * WAVE + lane];   // < 1024: in the slice
-            if (WB) {
 #pragma unroll
-                for (int u = 0; u < G; ++u) {
-                    const int e = g0 + u * WAVE + lane;
-                    xv[u] = x[(e < n && v[u].x < nvox) ? v[u].x : 0u];
+            for (int u = 0; u < G; ++u) {
+                const int e = g0 + u * WAVE + lane;
+                if (PACK) {
+                    const uint32_t ix = v[u].x & ((1u << PACK_Y) - 1u);
+                    const uint32_t iy = (v[u].x >> PACK_Y) & ((1u << (PACK_Z - PACK_Y)) - 1u);
+                    const uint32_t iz = v[u].x >> PACK_Z;
+                    // (24-bit operands: x < 1024, y, z < 2048, bricks per row <= 128)
+                    col[u] = __umul24(gn[0], __umul24(gn[1], iz) + iy) + ix;
+                    const uint32_t brick = __umul24(__umul24(iz, nby) + (iy >> 3), nbx) + (ix >> 3);
+                    const bool in = e < n && ix < gn[0] && iy < gn[1] && iz < gn[2];
+                    xi[u] = in ? (brick << 6) + ((iy & 7u) << 3) + (ix & 7u) : 0u;
+                } else {
+                    col[u] = v[u].x;
+                    xi[u] = (e < n && v[u].x < nvox) ? v[u].x : 0u;
                 }
+            }
+            if (WB) {
+                const PCT_GLOBAL float *src = PACK ? xb : x;
+#pragma unroll
+                for (int u = 0; u < G; ++u) xv[u] = src[xi[u]];
             }
 #pragma unroll
             for (int u = 0; u < G; ++u) {
                 const int e = g0 + u * WAVE + lane;
                 if (e < m) {
                     const float sv = cst ? chord : __uint_as_float(v[u].y);
-                    cols[e] = (int32_t)v[u].x;
+                    cols[e] = (int32_t)col[u];
                     if (HALF) vh[e] = __half_as_ushort(__float2half_rn(sv));
                     else vf[e] = sv;
                 }
@@ -660,14 +684,21 @@ struct RowOut {
         }
         __builtin_amdgcn_wave_barrier();
     }
-    __device__ __forceinline__ void flush(int n, int lane) {
+    template <bool PACK>
+    __device__ __forceinline__ void flush_p(int n, int lane) {
         if (want_b) {
-            if (half) flush_t<true, true>(n, lane);
-            else flush_t<true, false>(n, lane);
+            if (half) flush_t<true, true, PACK>(n, lane);
+            else flush_t<true, false, PACK>(n, lane);
         } else {
-            if (half) flush_t<false, true>(n, lane);
-            else flush_t<false, false>(n, lane);
+            if (half) flush_t<false, true, PACK>(n, lane);
+            else flush_t<false, false, PACK>(n, lane);
         }
+    }
+    // MAYPACK: a 3D emit, whose rows may hold packed coordinates
+    template <bool MAYPACK>
+    __device__ __forceinline__ void flush(int n, int lane) {
+        if (MAYPACK && pack) flush_p<true>(n, lane);
+        else flush_p<false>(n, lane);
     }
 };
 
@@ -848,6 +879,18 @@ __device__ __forceinline__ int32_t col_at(const int32_t stride[3], const int I[3
     return DIM == 3 ? I[0] + stride[1] * I[1] + stride[2] * I[2] : I[0] + stride[1] * I[1];
 }
 
+// What a staged entry holds for its voxel: the column, or for a 3D job with a bricked
+// copy of x its packed coordinates (x in bits 0-9, y in bits 10-20, z in bits 21-31),
+// which the copy-out turns into the column and the brick address.  Both are sums of the
+// per-axis steps below, so the walks that stage entries use them unchanged.
+template <int DIM>
+__device__ __forceinline__ void stage_strides(const JobDev &J, int32_t stride[3]) {
+    const bool pack = DIM == 3 && J.xb != nullptr;
+    stride[0] = 1;
+    stride[1] = pack ? (1 << PACK_Y) : J.n[0];
+    stride[2] = pack ? (1 << PACK_Z) : J.n[0] * J.n[1];
+}
+
 // Walk one row with the whole wave; n_entries = entries produced.
 // FAST: every item crosses each axis at most once (the row's `fast` flag).
 // RAY: a straight row (kind 1) with FAST: every lane takes the one ray, whose constants
@@ -898,7 +941,8 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, Lds
         P.tS = R(0);
         P.tE = R(0);
     }
-    const int32_t stride[3] = {1, J.n[0], J.n[0] * J.n[1]};
+    int32_t stride[3];
+    stage_strides<DIM>(J, stride);
     const float hf[3] = {(float)J.h[0], (float)J.h[1], (float)J.h[2]};
 
     // pass 1: voxel at the first item end, crossings up to the last one
@@ -1067,7 +1111,8 @@ __device__ __forceinline__ void wave_ray_row(const JobDev &J, RowRefD<double, DI
     int ctot;
     const int Pc = wave_excl_scan(c, ctot);
 
-    const int32_t stride[3] = {1, J.n[0], J.n[0] * J.n[1]};
+    int32_t stride[3];
+    stage_strides<DIM>(J, stride);
     R inv[3] = {R(0), R(0), R(0)}, tA[3] = {R(0), R(0), R(0)};
     int32_t dcol[3] = {0, 0, 0};
     R tprev = P.tS;   // the row's start point, unless a face lies between it and ta
@@ -1306,6 +1351,13 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
         if (!valid && lane == 0) set_status_dev(status, PCT_EINTERNAL);   // not a description of the count pass
         const bool mine = valid && kind != 3;   // kind 3: walked by the per-lane kernel
         out.x = gptr(J.x);
+        out.pack = DIM == 3 && J.xb != nullptr;
+        out.xb = gptr((const float *)J.xb);
+        out.gn[0] = (uint32_t)J.n[0];
+        out.gn[1] = (uint32_t)J.n[1];
+        out.gn[2] = (uint32_t)J.n[2];
+        out.nbx = (uint32_t)J.nbx;
+        out.nby = (uint32_t)J.nby;
         out.wepl = 0.f;
         out.wacc = TW(0);
         out.half = (J.val_dtype == PCT_F16);
@@ -1352,11 +1404,11 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
         if (ne <= STAGE_ROW_MAX) {
             out.commit(lane);
             if (ne > 0) {
-                out.flush((int)ne, lane);
+                out.template flush<DIM == 3>((int)ne, lane);
                 out.fold();
             }
         } else {
-            out.flush((int)min(ne, (int64_t)(STAGE_CAP + 1)), lane);
+            out.template flush<DIM == 3>((int)min(ne, (int64_t)(STAGE_CAP + 1)), lane);
             out.fold();
             out.commit(lane);
         }
