@@ -123,6 +123,28 @@ __device__ __forceinline__ RowRefD<R, DIM> row_ref(char *rowbuf, const JobDev &J
     (w).template at<typename std::remove_reference<decltype(((RowV<R> *)nullptr)->member)>::type>( \
         __builtin_offsetof(RowV<R>, member))
 
+// Lane i's value of v, as a wave-uniform value.
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int i) {
+    const uint64_t u = (uint64_t)v;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, i);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), i);
+    return (int64_t)(lo | (hi << 32));
+}
+
+// A field of the current row's description, read from the wave's LDS copy (one read
+// for the wave, no trip to memory) and made wave-uniform.
+__device__ __forceinline__ int32_t uniform_i32(const LdsRow &wl, size_t off) {
+    return __builtin_amdgcn_readfirstlane(wl.template at<int32_t>(off));
+}
+__device__ __forceinline__ double uniform_f64(const LdsRow &wl, size_t off) {
+    const uint2 v = wl.template at<uint2>(off);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)v.x);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)v.y);
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+#define RL_I32(wl, member) uniform_i32((wl), __builtin_offsetof(RowV<R>, member))
+#define RL_F64(wl, member) uniform_f64((wl), __builtin_offsetof(RowV<R>, member))
+
 template <typename R> __device__ __forceinline__ R r_fmax(R a, R b) {
     if constexpr (std::is_same<R, float>::value) return fmaxf(a, b); else return fmax(a, b);
 }
@@ -568,13 +590,6 @@ static_assert(rv_bytes<double>() % 16 == 0 && STAGE_ROW_MAX % 2 == 0, "the copy 
 #define PCT_GLOBAL __attribute__((address_space(1)))
 template <typename T> __device__ __forceinline__ PCT_GLOBAL T *gptr(T *p) { return (PCT_GLOBAL T *)p; }
 
-// Load of a value that no kernel of the pass writes, at an address the same in every lane,
-// through the constant address space: a scalar load, whose wait does not also wait for the
-// wave's vector stores and gathers still in flight (those share the vector memory counter,
-// which retires in issue order).
-template <typename T> __device__ __forceinline__ T load_uniform(const T *p) {
-    return *(const __attribute__((address_space(4))) T *)p;
-}
 
 // Bit offsets of y and z in the packed voxel coordinates of a staged entry (stage_strides).
 constexpr int PACK_Y = 10, PACK_Z = 21;
@@ -896,14 +911,14 @@ __device__ __forceinline__ void stage_strides(const JobDev &J, int32_t stride[3]
 // RAY: a straight row (kind 1) with FAST: every lane takes the one ray, whose constants
 // are the same in all lanes.
 template <typename R, int DIM, typename TW, bool FAST, bool RAY = false>
-__device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, LdsRow wl, int kind, RowOut<TW> &out,
+__device__ __forceinline__ void wave_row(const JobDev &J, LdsRow wl, int kind, RowOut<TW> &out,
                                          int lane, int64_t &n_entries) {
     // item counts as the count pass writes them; the bounds only matter for a
     // description it did not write (the walk then stays finite and the count check fails)
     const int mmax = J.nmax + 1;
-    const int M0 = min(max(RV(w, ray[0].M), 0), mmax);
-    const int Ns = (!RAY && kind == 2) ? min(max(RV(w, spl.N), 0), (1 << 22) + 1) : 0;
-    const int M1 = (!RAY && kind == 2) ? min(max(RV(w, ray[1].M), 0), mmax) : 0;
+    const int M0 = min(max(RL_I32(wl, ray[0].M), 0), mmax);
+    const int Ns = (!RAY && kind == 2) ? min(max(RL_I32(wl, spl.N), 0), (1 << 22) + 1) : 0;
+    const int M1 = (!RAY && kind == 2) ? min(max(RL_I32(wl, ray[1].M), 0), mmax) : 0;
     const int T = M0 + Ns + M1;
     n_entries = 0;
     if (T == 0) return;
@@ -954,10 +969,16 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, Lds
         piece_voxel<R, DIM>(P, Fs, Is, frs);
         bool mono = true;
         if (spl) {
+            // the turning windows from the LDS copy, all read before any is used
+            int32_t win[3][4];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) win[d][k] = RV(wl, spl.win[d][k]);
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-                mono = mono && !(first < RV(w, spl.win[d][1]) && last > RV(w, spl.win[d][0]));
-                mono = mono && !(first < RV(w, spl.win[d][3]) && last > RV(w, spl.win[d][2]));
+                mono = mono & !((first < win[d][1]) & (last > win[d][0]));
+                mono = mono & !((first < win[d][3]) & (last > win[d][2]));
             }
         }
         if (mono) {
@@ -1074,15 +1095,17 @@ __device__ __forceinline__ void wave_row(const JobDev &J, RowRefD<R, DIM> w, Lds
 // row's start point), so no lane needs the others' lengths and there is nothing to
 // stitch.  Parameters are FP64; a parameter step is rounded to FP32 once.
 template <int DIM, typename TW>
-__device__ __forceinline__ void wave_ray_row(const JobDev &J, RowRefD<double, DIM> w, RowOut<TW> &out, int lane,
-                                             int64_t &n_entries) {
+__device__ __forceinline__ void wave_ray_row(const JobDev &J, RowRefD<double, DIM> w, LdsRow wl, RowOut<TW> &out,
+                                             int lane, int64_t &n_entries) {
     using R = double;
-    const int M = min(max(RV(w, ray[0].M), 0), J.nmax + 1);
+    const int M = min(max(RL_I32(wl, ray[0].M), 0), J.nmax + 1);
     n_entries = 0;
     if (M == 0) return;
     const int K = (M + WAVE - 1) / WAVE;
     const int last_lane = (M + K - 1) / K - 1;
     LaneP<R> P;
+    // the ray, the same in every lane, with scalar loads (read from the LDS copy it was
+    // as fast in 2D and 1% slower in 3D)
     lane_ray<R, DIM, 0>(J, w, P);
     const int base = lane * K;
     const bool has_items = base < M;
@@ -1337,16 +1360,28 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
     if (r0 < rend && lane < NC) dbuf[lane] = row_ref<R, DIM>(rowbuf, J, r0).template at<uint4>((size_t)lane * 16);
     __builtin_amdgcn_wave_barrier();
     const LdsRow wl{(char *)dbuf};
+    // the rows' CSR bounds, read once per wave (lane l: row_ptr[r0 + l] and the next), so
+    // that a row takes its pair with readlane instead of a trip to memory
+    int64_t rp_a = 0, rp_b = 0;
+    if (STORE && r0 + lane < rend) {
+        rp_a = J.row_ptr[r0 + lane];
+        rp_b = J.row_ptr[r0 + lane + 1];
+    }
+    // waited for here, once: a use inside the row loop would make every row wait for all
+    // of its loads and stores in flight
+    asm volatile("" ::"v"(rp_a), "v"(rp_b));
     bool bad = false;
     for (int64_t r = r0; r < rend; ++r) {
-        const RowRefD<R, DIM> w = row_ref<R, DIM>(rowbuf, J, r);
         RowOut<TW> out;
         out.dbuf = dbuf;
         out.dnc = NC;
         out.dnext = make_uint4(0u, 0u, 0u, 0u);
         if (lane < NC)   // the next row's description (the last row's own at the end of the range)
             out.dnext = row_ref<R, DIM>(rowbuf, J, r + 1 < rend ? r + 1 : r).template at<uint4>((size_t)lane * 16);
-        const int kind = RV(w, kind);
+        // (the control fields from the LDS copy, which holds this row's description)
+        const int kind = RL_I32(wl, kind);
+        const int fast = RL_I32(wl, fast);
+        const double bfac = RL_F64(wl, bfac);
         const bool valid = kind >= 0 && kind <= 3;
         if (!valid && lane == 0) set_status_dev(status, PCT_EINTERNAL);   // not a description of the count pass
         const bool mine = valid && kind != 3;   // kind 3: walked by the per-lane kernel
@@ -1370,8 +1405,9 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
         out.chord = J.chord;
         int64_t pos = 0;
         if (out.store) {
-            pos = load_uniform(J.row_ptr + r);
-            const int64_t end = load_uniform(J.row_ptr + r + 1);
+            const int i = (int)(r - r0);   // < 64
+            pos = readlane_i64(rp_a, i);
+            const int64_t end = readlane_i64(rp_b, i);
             if (pos < 0 || end < pos || end > J.cap) {
                 if (lane == 0) set_status_dev(status, PCT_ECAPACITY);
                 out.store = false;
@@ -1386,15 +1422,15 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
         int64_t ne = 0;
         if (mine && kind != 0) {
             if constexpr (std::is_same<R, double>::value) {
-                if (kind == 1) wave_ray_row<DIM, TW>(J, w, out, lane, ne);
-                else if (RV(w, fast)) wave_row<R, DIM, TW, true>(J, w, wl, kind, out, lane, ne);
-                else wave_row<R, DIM, TW, false>(J, w, wl, kind, out, lane, ne);
+                if (kind == 1) wave_ray_row<DIM, TW>(J, row_ref<R, DIM>(rowbuf, J, r), wl, out, lane, ne);
+                else if (fast) wave_row<R, DIM, TW, true>(J, wl, kind, out, lane, ne);
+                else wave_row<R, DIM, TW, false>(J, wl, kind, out, lane, ne);
             } else {
-                if (RV(w, fast)) {
-                    if (kind == 1) wave_row<R, DIM, TW, true, true>(J, w, wl, kind, out, lane, ne);
-                    else wave_row<R, DIM, TW, true>(J, w, wl, kind, out, lane, ne);
+                if (fast) {
+                    if (kind == 1) wave_row<R, DIM, TW, true, true>(J, wl, kind, out, lane, ne);
+                    else wave_row<R, DIM, TW, true>(J, wl, kind, out, lane, ne);
                 } else {
-                    wave_row<R, DIM, TW, false>(J, w, wl, kind, out, lane, ne);
+                    wave_row<R, DIM, TW, false>(J, wl, kind, out, lane, ne);
                 }
             }
         }
@@ -1417,7 +1453,7 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
             if (STORE && out.store && ne != out.len && lane == 0) set_status_dev(status, PCT_EINTERNAL);
             if (out.want_b) {
                 const TW bs = (TW)wave_sum((double)out.wacc);
-                if (lane == 0) *gptr(J.b + r) = (float)(bs * (TW)RV(w, bfac));
+                if (lane == 0) *gptr(J.b + r) = (float)(bs * (TW)bfac);
             }
         }
     }
