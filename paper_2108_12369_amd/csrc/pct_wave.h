@@ -477,27 +477,6 @@ __device__ __forceinline__ int64_t spline_axis_crossings(const LaneP<R> &p, int 
     return c + abs(axis_index<R>(p, d, R(p.M)) - Iprev);
 }
 
-// Crossings of the items between item ends j0 < j1 by walking them.
-template <typename R, int DIM>
-__device__ __forceinline__ int walk_count(const LaneP<R> &p, int j0, const int I0[3], int j1) {
-    int c = 0;
-    int Ip[3] = {I0[0], I0[1], I0[2]};
-    R mf = R(j0);
-    for (int j = j0 + 1; j <= j1; ++j) {
-        mf += R(1);
-        R F[3], fr[3];
-        int I[3];
-        piece_next<R, DIM>(p, j, mf, F);
-        piece_voxel<R, DIM>(p, F, I, fr);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            c += abs(I[d] - Ip[d]);
-            Ip[d] = I[d];
-        }
-    }
-    return c;
-}
-
 // ------------------------------------------------------------------ wave helpers
 // Inclusive add-scan over the wavefront with DPP: shifts by 1, 2, 4, 8 inside each row
 // of 16 lanes, then the last lane of row 0 / rows 0-1 is added to the rows after it.
@@ -960,14 +939,22 @@ __device__ __forceinline__ void wave_row(const JobDev &J, LdsRow wl, int kind, R
     stage_strides<DIM>(J, stride);
     const float hf[3] = {(float)J.h[0], (float)J.h[1], (float)J.h[2]};
 
-    // pass 1: voxel at the first item end, crossings up to the last one
+    // pass 1: voxel at the first item end, crossings up to the last one.  Per axis, the
+    // difference of the end indices, or, where the lane's items reach into one of the
+    // axis' turning windows (the coordinate need not be monotone there), the sum of that
+    // axis' index steps over the lane's items -- the same count, axis by axis, that a walk
+    // of all the items' voxels would give.  Only the axes some lane must walk are walked.
     int Is[3] = {0, 0, 0};
     R Fs[3] = {R(0), R(0), R(0)}, frs[3] = {R(0), R(0), R(0)};
     int c = 0;
     {
         piece_point<R, DIM>(P, first, R(first), Fs);
         piece_voxel<R, DIM>(P, Fs, Is, frs);
-        bool mono = true;
+        R Fe[3], fre[3];
+        int Ie[3];
+        piece_point<R, DIM>(P, last, R(last), Fe);
+        piece_voxel<R, DIM>(P, Fe, Ie, fre);
+        bool walk[3] = {false, false, false};
         if (spl) {
             // the turning windows from the LDS copy, all read before any is used
             int32_t win[3][4];
@@ -976,20 +963,23 @@ __device__ __forceinline__ void wave_row(const JobDev &J, LdsRow wl, int kind, R
 #pragma unroll
                 for (int k = 0; k < 4; ++k) win[d][k] = RV(wl, spl.win[d][k]);
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-                mono = mono & !((first < win[d][1]) & (last > win[d][0]));
-                mono = mono & !((first < win[d][3]) & (last > win[d][2]));
-            }
+            for (int d = 0; d < DIM; ++d)
+                walk[d] = ((first < win[d][1]) & (last > win[d][0])) | ((first < win[d][3]) & (last > win[d][2]));
         }
-        if (mono) {
-            R Fe[3], fre[3];
-            int Ie[3];
-            piece_point<R, DIM>(P, last, R(last), Fe);
-            piece_voxel<R, DIM>(P, Fe, Ie, fre);
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) c += abs(Ie[d] - Is[d]);
-        } else {
-            c = walk_count<R, DIM>(P, first, Is, last);
+        for (int d = 0; d < DIM; ++d) {
+            int cd = abs(Ie[d] - Is[d]);
+            if (__builtin_amdgcn_ballot_w64(walk[d]) != 0) {   // uniform
+                int steps = 0, Ip = Is[d];
+                for (int it = 0; it < K; ++it) {
+                    const int m = min(first + it + 1, last);   // item end (the last one again past it)
+                    const int I = axis_index<R>(P, d, R(m));
+                    steps += abs(I - Ip);
+                    Ip = I;
+                }
+                cd = walk[d] ? steps : cd;
+            }
+            c += cd;
         }
     }
     int ctot;
