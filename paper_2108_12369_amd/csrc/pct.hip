@@ -72,7 +72,7 @@ static Layout layout_of(int32_t n_jobs, const int64_t *row_counts, const size_t 
     L.total_rows = rows;
     L.jobs_off = align256(sizeof(WsHeader));
     L.order_off = align256(L.jobs_off + (size_t)n_jobs * sizeof(JobDev));
-    L.sums_off = align256(L.order_off + (size_t)n_jobs * sizeof(int32_t));
+    L.sums_off = align256(L.order_off + 2 * (size_t)n_jobs * sizeof(int32_t));   // emit order, count order
     L.offs_off = align256(L.sums_off + (size_t)(tiles + 1) * sizeof(int64_t));
     L.flags_off = align256(L.offs_off + (size_t)(tiles + 1) * sizeof(int64_t));
     L.counts_off = align256(L.flags_off + (size_t)(tiles + 1) * sizeof(int32_t));
@@ -148,15 +148,16 @@ __global__ void k_reset_queue(WsHeader *h) {
 
 __device__ __forceinline__ void set_status(int32_t *status, int32_t code) { set_status_dev(status, code); }
 
-// Tile -> job: jobs are laid out in tile order; binary search on tile_base.
-__device__ __forceinline__ int job_of_tile(const JobDev *jobs, int n_jobs, int64_t tile) {
+// Count tile -> job: the jobs' count tiles follow the count order (corder: the 2D jobs,
+// then the 3D jobs, each in the caller's order); binary search on their tile_base.
+__device__ __forceinline__ int job_of_tile(const JobDev *jobs, const int32_t *corder, int n_jobs, int64_t tile) {
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile_base <= tile) lo = mid;
+        if (jobs[corder[mid]].tile_base <= tile) lo = mid;
         else hi = mid - 1;
     }
-    return lo;
+    return corder[lo];
 }
 
 // Emit tile -> job: the jobs are laid out in launch order (eorder); binary search on
@@ -188,14 +189,15 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *lds) {
 // instance per grid dimension: a block whose job has the other dimension leaves at once
 // and writes nothing (the other instance's launch covers its tile).
 template <typename R, bool COUNT, int DIM>
-__global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs, int n_jobs,
-                                                int32_t *__restrict__ counts, int64_t *__restrict__ tile_sums,
-                                                int32_t *__restrict__ tile_flags, char *__restrict__ rowbuf) {
+__global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs, const int32_t *__restrict__ corder,
+                                                int n_jobs, int32_t *__restrict__ counts,
+                                                int64_t *__restrict__ tile_sums, int32_t *__restrict__ tile_flags,
+                                                char *__restrict__ rowbuf, int64_t tile_base) {
     __shared__ int64_t red[TILE / 64];
-    const int64_t tile = blockIdx.x;
-    const int jid = job_of_tile(jobs, n_jobs, tile);
+    const int64_t tile = tile_base + blockIdx.x;   // the tiles of DIM's jobs are one range
+    const int jid = job_of_tile(jobs, corder, n_jobs, tile);
     const JobDev &J = jobs[jid];
-    if (J.dim != DIM) return;   // block-uniform
+    if (J.dim != DIM) return;   // block-uniform (never, with the range right)
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     int64_t cnt = 0;
     int lane_walk = 0;
@@ -217,11 +219,17 @@ __global__ void __launch_bounds__(TILE) k_count(const JobDev *__restrict__ jobs,
 }
 
 // The count kernel's launches for a batch: one per grid dimension present.
+// One instance per grid dimension, over that dimension's count tiles only (cbase,
+// ctiles: the first tile and the tile count of the 2D jobs, then of the 3D jobs).
 template <typename R, bool COUNT>
-void launch_count(bool has2, bool has3, dim3 grid, hipStream_t s, const JobDev *J, int n_jobs, int32_t *counts,
-                  int64_t *sums, int32_t *flags, char *rows) {
-    if (has2) hipLaunchKernelGGL((k_count<R, COUNT, 2>), grid, dim3(TILE), 0, s, J, n_jobs, counts, sums, flags, rows);
-    if (has3) hipLaunchKernelGGL((k_count<R, COUNT, 3>), grid, dim3(TILE), 0, s, J, n_jobs, counts, sums, flags, rows);
+void launch_count(const int64_t cbase[2], const int64_t ctiles[2], hipStream_t s, const JobDev *J,
+                  const int32_t *corder, int n_jobs, int32_t *counts, int64_t *sums, int32_t *flags, char *rows) {
+    if (ctiles[0] > 0)
+        hipLaunchKernelGGL((k_count<R, COUNT, 2>), dim3((unsigned)ctiles[0]), dim3(TILE), 0, s, J, corder, n_jobs,
+                           counts, sums, flags, rows, cbase[0]);
+    if (ctiles[1] > 0)
+        hipLaunchKernelGGL((k_count<R, COUNT, 3>), dim3((unsigned)ctiles[1]), dim3(TILE), 0, s, J, corder, n_jobs,
+                           counts, sums, flags, rows, cbase[1]);
 }
 
 // Grid dimensions present among the jobs that have rows.
@@ -272,12 +280,12 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_tiles(const JobDev *__res
 }
 
 // row_ptr[r] = (offset of the tile within its job) + exclusive scan of the tile's counts.
-__global__ void __launch_bounds__(TILE) k_row_ptr(const JobDev *__restrict__ jobs, int n_jobs,
-                                                  const int32_t *__restrict__ counts,
+__global__ void __launch_bounds__(TILE) k_row_ptr(const JobDev *__restrict__ jobs, const int32_t *__restrict__ corder,
+                                                  int n_jobs, const int32_t *__restrict__ counts,
                                                   const int64_t *__restrict__ offs) {
     __shared__ int64_t sc[TILE];
     const int64_t tile = blockIdx.x;
-    const int jid = job_of_tile(jobs, n_jobs, tile);
+    const int jid = job_of_tile(jobs, corder, n_jobs, tile);
     const JobDev &J = jobs[jid];
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     const int64_t c = (r < J.row_count) ? counts[J.count_off + r] : 0;
@@ -294,14 +302,15 @@ __global__ void __launch_bounds__(TILE) k_row_ptr(const JobDev *__restrict__ job
 
 // Wave-cooperative emit: each wavefront of the block takes 64 rows of the tile.
 
-// One instance per grid dimension (the register needs differ); blocks of jobs of the
-// other dimension return at once.  A block is one emit tile: 4 waves of rpw rows.
+// One instance per grid dimension (the register needs differ), launched over that
+// dimension's emit tiles only: they are one range, [tile_base, tile_base + gridDim.x),
+// of the launch order.  A block is one emit tile: 4 waves of rpw rows.
 template <typename R, bool STORE, int DIM>
 __global__ void __launch_bounds__(TILE) k_emit_wave(const JobDev *__restrict__ jobs, const int32_t *__restrict__ eorder,
                                                     int n_jobs, char *__restrict__ rowbuf,
-                                                    int32_t *__restrict__ status) {
+                                                    int32_t *__restrict__ status, int64_t tile_base) {
     __shared__ __attribute__((aligned(16))) uint2 stage[TILE / WAVE][STAGE_CAP + 1];   // 1024 slots per wave
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = tile_base + blockIdx.x;
     const int jid = job_of_etile(jobs, eorder, n_jobs, tile);
     const JobDev &J = jobs[jid];
     if (J.dim != DIM) return;
@@ -349,13 +358,13 @@ __global__ void __launch_bounds__(TILE) k_emit_queue(const JobDev *__restrict__ 
 
 // Rows whose spline may leave the grid box: one lane per row.
 template <typename R, bool STORE>
-__global__ void __launch_bounds__(TILE) k_emit_lane(const JobDev *__restrict__ jobs, int n_jobs,
-                                                    char *__restrict__ rowbuf,
+__global__ void __launch_bounds__(TILE) k_emit_lane(const JobDev *__restrict__ jobs, const int32_t *__restrict__ corder,
+                                                    int n_jobs, char *__restrict__ rowbuf,
                                                     const int32_t *__restrict__ tile_flags,
                                                     int32_t *__restrict__ status) {
     const int64_t tile = blockIdx.x;
     if (tile_flags[tile] == 0) return;   // no row of this tile needs the per-lane walk
-    const int jid = job_of_tile(jobs, n_jobs, tile);
+    const int jid = job_of_tile(jobs, corder, n_jobs, tile);
     const JobDev &J = jobs[jid];
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     if (r >= J.row_count) return;
@@ -836,7 +845,7 @@ struct HostJobs {
     static constexpr int FIXED = 64;
     int64_t rc_fixed[FIXED];
     JobDev jobs_fixed[FIXED];
-    int32_t order_fixed[FIXED];
+    int32_t order_fixed[FIXED * 2];   // emit order, then count order
     double cost_fixed[FIXED];
     size_t bb_fixed[FIXED];
     std::vector<int64_t> rc_heap;
@@ -853,7 +862,7 @@ struct HostJobs {
         if (n > FIXED) {
             rc_heap.resize(n);
             jobs_heap.resize(n);
-            order_heap.resize(n);
+            order_heap.resize(2 * (size_t)n);
             cost_heap.resize(n);
             bb_heap.resize(n);
             rc = rc_heap.data();
@@ -873,6 +882,7 @@ struct Prepared {
     pct_launch_config cfg = DEFAULT_CFG;
     int64_t total_etiles = 0;
     int64_t dim_base[2] = {0, 0}, dim_tiles[2] = {0, 0};   // emit tiles of the 2D jobs, then the 3D jobs
+    int64_t cdim_base[2] = {0, 0}, cdim_tiles[2] = {0, 0}; // count tiles likewise
     bool any_bricks = false;                                 // some job has a bricked copy of x to fill
     explicit Prepared(int32_t n) : H(n) {}
 };
@@ -891,12 +901,11 @@ static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
     }
     P.L = layout_of(n_jobs, rc, bb);
     if (!ws || ws_bytes < P.L.total) return PCT_EWORKSPACE;
-    int64_t count_off = 0, tile_base = 0;
+    int64_t count_off = 0;
     size_t boff = P.L.bricks_off;
     for (int j = 0; j < n_jobs; ++j) {
-        jd[j] = make_job(jobs[j], count_off, tile_base);
+        jd[j] = make_job(jobs[j], count_off, 0);
         count_off += rc[j];
-        tile_base += jd[j].n_tiles;
         if (bb[j] > 0 && jobs[j].x_dev) {
             jd[j].xb = reinterpret_cast<float *>((char *)ws + boff);
             jd[j].nbx = (jd[j].n[0] + 7) / 8;
@@ -904,6 +913,26 @@ static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
             P.any_bricks = true;
         }
         boff += align256(bb[j]);
+    }
+    // count tiles (and the row descriptions stored per tile): the 2D jobs, then the 3D
+    // jobs, each in the caller's order, so that each dimension's count kernel takes one
+    // range of tiles; independent of the launch configuration, so that a count and an
+    // emit under different configurations agree
+    int32_t *corder = P.H.order + n_jobs;
+    {
+        int k = 0;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j < n_jobs; ++j)
+                if ((jd[j].dim == 3) == (pass == 1)) corder[k++] = j;
+        int64_t tile = 0;
+        for (int k2 = 0; k2 < n_jobs; ++k2) {
+            JobDev &J = jd[corder[k2]];
+            J.tile_base = tile;
+            const int di = J.dim == 3 ? 1 : 0;
+            if (P.cdim_tiles[di] == 0) P.cdim_base[di] = tile;
+            P.cdim_tiles[di] += J.n_tiles;
+            tile += J.n_tiles;
+        }
     }
     const pct_launch_config cfg = g_cfg;
     P.cfg = cfg;
@@ -952,12 +981,13 @@ static pct_status prepare(int32_t n_jobs, const pct_job *jobs, void *ws, size_t 
         for (int k = 0; k < pack.count; ++k) pack.jobs[k] = jd[first + k];
         hipLaunchKernelGGL(k_put_jobs, dim3(1), dim3(256), 0, st, dst, pack);
     }
+    // the emit order, then the count order
     int32_t *odst = reinterpret_cast<int32_t *>(w + P.L.order_off);
-    for (int first = 0; first < n_jobs; first += ORDER_PER_PACK) {
+    for (int first = 0; first < 2 * n_jobs; first += ORDER_PER_PACK) {
         OrderPack pack;
         memset(&pack, 0, sizeof pack);
         pack.first = first;
-        pack.count = (n_jobs - first < ORDER_PER_PACK) ? n_jobs - first : ORDER_PER_PACK;
+        pack.count = (2 * n_jobs - first < ORDER_PER_PACK) ? 2 * n_jobs - first : ORDER_PER_PACK;
         for (int k = 0; k < pack.count; ++k) pack.idx[k] = order[first + k];
         hipLaunchKernelGGL(k_put_order, dim3(1), dim3(256), 0, st, odst, pack);
     }
@@ -982,11 +1012,14 @@ static void launch_emit(const Prepared &P, bool has2, bool has3, hipStream_t s, 
             hipLaunchKernelGGL((k_emit_queue<R, STORE, 3>), dim3((unsigned)(n3 < cap ? n3 : cap)), block, 0, s, J,
                                eorder, n_jobs, rb, status, &hdr->qnext[1], P.dim_base[1], n3);
     } else {
-        const dim3 egrid((unsigned)P.total_etiles);
-        if (has2) hipLaunchKernelGGL((k_emit_wave<R, STORE, 2>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
-        if (has3) hipLaunchKernelGGL((k_emit_wave<R, STORE, 3>), egrid, block, 0, s, J, eorder, n_jobs, rb, status);
+        if (has2 && P.dim_tiles[0] > 0)
+            hipLaunchKernelGGL((k_emit_wave<R, STORE, 2>), dim3((unsigned)P.dim_tiles[0]), block, 0, s, J, eorder,
+                               n_jobs, rb, status, P.dim_base[0]);
+        if (has3 && P.dim_tiles[1] > 0)
+            hipLaunchKernelGGL((k_emit_wave<R, STORE, 3>), dim3((unsigned)P.dim_tiles[1]), block, 0, s, J, eorder,
+                               n_jobs, rb, status, P.dim_base[1]);
     }
-    hipLaunchKernelGGL((k_emit_lane<R, STORE>), grid, block, 0, s, J, n_jobs, rb, flags, status);
+    hipLaunchKernelGGL((k_emit_lane<R, STORE>), grid, block, 0, s, J, eorder + n_jobs, n_jobs, rb, flags, status);
 }
 
 }  // namespace pct
@@ -1088,22 +1121,21 @@ static pct_status count_common(int32_t n_jobs, const pct_job *jobs, void *ws, si
     if (clear_status) hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, (WsHeader *)w);
     if (n_jobs == 0) return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
     const JobDev *J = (const JobDev *)(w + P.L.jobs_off);
+    const int32_t *corder = (const int32_t *)(w + P.L.order_off) + n_jobs;
     int64_t *sums = (int64_t *)(w + P.L.sums_off);
     int64_t *offs = (int64_t *)(w + P.L.offs_off);
     int32_t *counts = (int32_t *)(w + P.L.counts_off);
     const int64_t T = P.L.total_tiles;
     if (T > 0) {
-        bool has2, has3;
-        dims_present(n_jobs, jobs, has2, has3);
         if (jobs[0].precision == PCT_MIXED)
-            launch_count<double, true>(has2, has3, dim3((unsigned)T), s, J, n_jobs, counts, sums,
+            launch_count<double, true>(P.cdim_base, P.cdim_tiles, s, J, corder, n_jobs, counts, sums,
                                        (int32_t *)(w + P.L.flags_off), w + P.L.rows_off);
         else
-            launch_count<float, true>(has2, has3, dim3((unsigned)T), s, J, n_jobs, counts, sums,
+            launch_count<float, true>(P.cdim_base, P.cdim_tiles, s, J, corder, n_jobs, counts, sums,
                                       (int32_t *)(w + P.L.flags_off), w + P.L.rows_off);
     }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(SCAN_THREADS), 0, s, J, n_jobs, T, sums, offs, nnz_total_dev);
-    if (T > 0) hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)T), dim3(TILE), 0, s, J, n_jobs, counts, offs);
+    if (T > 0) hipLaunchKernelGGL(k_row_ptr, dim3((unsigned)T), dim3(TILE), 0, s, J, corder, n_jobs, counts, offs);
     return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
 }
 
@@ -1141,11 +1173,15 @@ static pct_status emit_common(int32_t n_jobs, const pct_job *jobs, void *ws, siz
     char *rb = (char *)rows;
     WsHeader *hdr = (WsHeader *)w;
     if (mixed) {
-        if (!store) launch_count<double, false>(has2, has3, grid, s, J, n_jobs, nullptr, nullptr, flags, rb);
+        if (!store)
+            launch_count<double, false>(P.cdim_base, P.cdim_tiles, s, J, eorder + n_jobs, n_jobs, nullptr, nullptr,
+                                        flags, rb);
         if (store) launch_emit<double, true>(P, has2, has3, s, J, eorder, n_jobs, rb, flags, status, hdr, grid);
         else launch_emit<double, false>(P, has2, has3, s, J, eorder, n_jobs, rb, flags, status, hdr, grid);
     } else {
-        if (!store) launch_count<float, false>(has2, has3, grid, s, J, n_jobs, nullptr, nullptr, flags, rb);
+        if (!store)
+            launch_count<float, false>(P.cdim_base, P.cdim_tiles, s, J, eorder + n_jobs, n_jobs, nullptr, nullptr,
+                                       flags, rb);
         if (store) launch_emit<float, true>(P, has2, has3, s, J, eorder, n_jobs, rb, flags, status, hdr, grid);
         else launch_emit<float, false>(P, has2, has3, s, J, eorder, n_jobs, rb, flags, status, hdr, grid);
     }
