@@ -662,10 +662,11 @@ struct RowOut {
             for (int u = 0; u < G; ++u) {
                 const int e = g0 + u * WAVE + lane;
                 if (e < m) {
+                    // non-temporal: nothing here reads the output again, and x is kept in L2
                     const float sv = cst ? chord : __uint_as_float(v[u].y);
-                    cols[e] = (int32_t)col[u];
-                    if (HALF) vh[e] = __half_as_ushort(__float2half_rn(sv));
-                    else vf[e] = sv;
+                    __builtin_nontemporal_store((int32_t)col[u], &cols[e]);
+                    if (HALF) __builtin_nontemporal_store((uint16_t)__half_as_ushort(__float2half_rn(sv)), &vh[e]);
+                    else __builtin_nontemporal_store(sv, &vf[e]);
                 }
             }
             if (WB) {
