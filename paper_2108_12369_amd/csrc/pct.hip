@@ -450,13 +450,13 @@ __device__ __forceinline__ int region_box(const RegionDev &g, const double lo[3]
     return out ? -1 : 0;
 }
 
-__global__ void __launch_bounds__(256) k_phantom(PhantomArgs A, float *__restrict__ x, int64_t nvox) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nvox) return;
+// Voxel j (< 2^31: a grid has fewer voxels, see check_phantom) of the phantom A.
+__device__ __forceinline__ void phantom_voxel(const PhantomArgs &A, float *__restrict__ x, uint32_t j) {
+    const uint32_t n0 = (uint32_t)A.n[0], n1 = (uint32_t)A.n[1];
     int idx[3];
-    idx[0] = (int)(j % A.n[0]);
-    idx[1] = (int)((j / A.n[0]) % A.n[1]);
-    idx[2] = (int)(j / ((int64_t)A.n[0] * A.n[1]));
+    idx[0] = (int)(j % n0);
+    idx[1] = (int)((j / n0) % n1);
+    idx[2] = (int)(j / (n0 * n1));
     double val;
     if (A.voxelize == PCT_AREA_AVG) {
         // weighted-area average: the mean RSP over S^dim midpoints of the voxel; a voxel
@@ -547,6 +547,105 @@ __global__ void __launch_bounds__(256) k_phantom(PhantomArgs A, float *__restric
         val = sum / (double)nc;
     }
     x[j] = (float)val;
+}
+
+// Corner average of PV voxels that follow one another along the last axis L (y in 2D, z
+// in 3D), from voxel (i0, i1, i2) on; only cnt <= PV of them are written.  The corners
+// of these voxels lie on 2 grid lines across each other axis and on cnt + 1 along L, so
+// for a region whose axes are not turned each scaled coordinate (p - c) / s and its
+// square are taken once per line and shared by the corners on it.  A corner's sum of
+// squares is formed in the same order as in phantom_voxel ((s0 + s1) + s2, the leading
+// 0 + s0 being exact), so every voxel gets the value phantom_voxel gives it.
+constexpr int PV = 4;
+template <int DIM>
+__device__ __forceinline__ void phantom_corner_run(const PhantomArgs &A, float *__restrict__ x, int i0, int i1,
+                                                   int i2, int cnt) {
+    constexpr int L = DIM - 1, nc = 1 << DIM;
+    const int idx[3] = {i0, i1, i2};
+    // grid-line coordinates: pc[d][b], b < 2 across L, b <= PV along it
+    double pc[3][PV + 1];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int b = 0; b <= PV; ++b) pc[d][b] = d < DIM ? A.o[d] + (double)(idx[d] + b) * A.h[d] : 0.0;
+    float v[PV][nc];   // RSP at each corner (binary32 values, exact in binary64)
+#pragma unroll
+    for (int t = 0; t < PV; ++t)
+#pragma unroll
+        for (int c = 0; c < nc; ++c) v[t][c] = 0.f;
+    for (int k = 0; k < A.n_regions; ++k) {
+        const RegionDev &g = A.reg[k];
+        if (!g.rot) {
+            // squares of the scaled coordinates per line (unused on an axis the region lacks)
+            double sq[3][PV + 1];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int b = 0; b <= PV; ++b) {
+                    sq[d][b] = 0.0;
+                    if (d < DIM && (b < 2 || d == L) && d < g.axes) {
+                        const double u = (pc[d][b] - g.c[d]) / g.s[d];
+                        sq[d][b] = u * u;
+                    }
+                }
+#pragma unroll
+            for (int t = 0; t < PV; ++t)
+#pragma unroll
+                for (int c = 0; c < nc; ++c) {
+                    double q = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        if (i < g.axes) {
+                            const double si = sq[i][((c >> i) & 1) + (i == L ? t : 0)];
+                            q = i == 0 ? si : q + si;
+                        }
+                    }
+                    if (q <= 1.0) v[t][c] = g.rsp;
+                }
+        } else {
+#pragma unroll
+            for (int t = 0; t < PV; ++t)
+#pragma unroll
+                for (int c = 0; c < nc; ++c) {
+                    double p[3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) p[i] = pc[i][((c >> i) & 1) + (i == L ? t : 0)];
+                    if (region_q(g, p) <= 1.0) v[t][c] = g.rsp;
+                }
+        }
+    }
+    const int64_t n0 = A.n[0], n01 = (int64_t)A.n[0] * A.n[1];
+#pragma unroll
+    for (int t = 0; t < PV; ++t) {
+        if (t < cnt) {
+            double sum = 0.0;
+#pragma unroll
+            for (int c = 0; c < nc; ++c) sum += (double)v[t][c];
+            const int j1 = i1 + (L == 1 ? t : 0), j2 = i2 + (L == 2 ? t : 0);
+            x[i0 + n0 * j1 + n01 * j2] = (float)(sum / (double)nc);
+        }
+    }
+}
+
+// The corner rule: one thread per run of PV voxels along the last axis (x fastest, then
+// the other axis across it, then the run); the other rules: one thread per voxel.
+__global__ void __launch_bounds__(256) k_phantom(PhantomArgs A, float *__restrict__ x, int64_t nvox) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (A.voxelize != PCT_CORNER_AVG) {
+        if (j < nvox) phantom_voxel(A, x, (uint32_t)j);
+        return;
+    }
+    const uint32_t n0 = (uint32_t)A.n[0];
+    const uint32_t nacr = A.dim == 3 ? (uint32_t)A.n[1] : 1u;
+    const uint32_t nL = (uint32_t)A.n[A.dim - 1];
+    const uint32_t runs = (nL + PV - 1) / PV;
+    if (j >= (int64_t)n0 * nacr * runs) return;
+    const uint32_t jj = (uint32_t)j;
+    const int i0 = (int)(jj % n0);
+    const int ia = (int)((jj / n0) % nacr);
+    const int lo = (int)(jj / (n0 * nacr)) * PV, cnt = min(PV, (int)nL - lo);
+    if (A.dim == 3) phantom_corner_run<3>(A, x, i0, ia, lo, cnt);
+    else phantom_corner_run<2>(A, x, i0, lo, 0, cnt);
 }
 
 // ------------------------------------------------------------------ host helpers
@@ -1077,7 +1176,9 @@ pct_status pct_phantom_build(const pct_phantom *ph, float *x_dev, void *stream) 
         A.reg[k].hw[1] = sqrt(r.semi[0] * r.semi[0] * sr * sr + r.semi[1] * r.semi[1] * cr * cr);
     }
     const int64_t nv = n_voxels(ph);
-    const int64_t blocks = (nv + 255) / 256;
+    const int64_t nL = A.n[A.dim - 1];
+    const int64_t threads = A.voxelize == PCT_CORNER_AVG ? nv / nL * ((nL + PV - 1) / PV) : nv;
+    const int64_t blocks = (threads + 255) / 256;
     hipLaunchKernelGGL(k_phantom, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, A, x_dev, nv);
     return hipGetLastError() == hipSuccess ? PCT_OK : PCT_EHIP;
 }
@@ -1389,41 +1490,58 @@ pct_status pct_graph_create_sets(int32_t n_sets, const int32_t *set_sizes, const
         for (int64_t j = 0; j < total; ++j)
             if (!jobs[j].x_dev) return PCT_EINVAL;
     }
-    // The count pass does not read x, so the phantom builds form a branch of their own
-    // (stream s2, forked from and joined back into the capture stream s) that runs beside
-    // the first set's count pass; its emit, which gathers x, waits for both.  The sets
-    // follow one another on s: count, then emit, each into its own slice of nnz_total_dev.
+    // The count pass does not read x, so the phantom builds form branches of their own
+    // (streams b[0 .. NB-1], forked from and joined back into the capture stream s) that
+    // run beside the first set's count pass; its emit, which gathers x, waits for all of
+    // them.  The builds are dealt round-robin over the branches: one chain of small
+    // launches would outlast the count pass.  The sets follow one another on s: count,
+    // then emit, each into its own slice of nnz_total_dev.
+    constexpr int NB = 4;
     pct_status st = PCT_OK;
-    hipStream_t s = nullptr, s2 = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t s = nullptr, b[NB] = {};
+    hipEvent_t fork = nullptr, join[NB] = {};
     bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess &&
-              hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) == hipSuccess &&
-              hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&join, hipEventDisableTiming) == hipSuccess;
+              hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < NB && ok; ++i)
+        ok = hipStreamCreateWithFlags(&b[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&join[i], hipEventDisableTiming) == hipSuccess;
     bool capturing = ok && hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (!capturing) st = PCT_EHIP;
+    int nb = 0;   // branches in use
     if (st == PCT_OK && build_x) {
-        if (hipEventRecord(fork, s) != hipSuccess || hipStreamWaitEvent(s2, fork, 0) != hipSuccess) st = PCT_EHIP;
+        if (hipEventRecord(fork, s) != hipSuccess) st = PCT_EHIP;
         std::vector<const float *> done;
         for (int64_t j = 0; j < total && st == PCT_OK; ++j) {
             const float *x = jobs[j].x_dev;
             if (std::find(done.begin(), done.end(), x) != done.end()) continue;
+            const int i = (int)(done.size() % NB);
             done.push_back(x);
-            st = pct_phantom_build(jobs[j].phantom, const_cast<float *>(x), s2);
+            if (i >= nb) {
+                if (hipStreamWaitEvent(b[i], fork, 0) != hipSuccess) st = PCT_EHIP;
+                nb = i + 1;
+            }
+            if (st == PCT_OK) st = pct_phantom_build(jobs[j].phantom, const_cast<float *>(x), b[i]);
         }
     }
     for (int64_t k = 0, off = 0; k < n_sets && st == PCT_OK; off += set_sizes[k], ++k) {
         st = count_common(set_sizes[k], jobs + off, ws, ws_bytes, nnz_total_dev + off, s, k == 0);
-        if (st == PCT_OK && build_x && k == 0) {
-            if (hipEventRecord(join, s2) != hipSuccess || hipStreamWaitEvent(s, join, 0) != hipSuccess) st = PCT_EHIP;
-        }
+        for (int i = 0; i < nb && k == 0 && st == PCT_OK; ++i)
+            if (hipEventRecord(join[i], b[i]) != hipSuccess || hipStreamWaitEvent(s, join[i], 0) != hipSuccess)
+                st = PCT_EHIP;
         if (st == PCT_OK) st = pct_emit_csr(set_sizes[k], jobs + off, ws, ws_bytes, s);
     }
+    // a failed capture still has to be ended; branches forked from it must be joined
+    // for the end to succeed, which a failure above may have left undone (the graph is
+    // then discarded)
+    for (int i = 0; i < nb && st != PCT_OK && capturing; ++i)
+        if (hipEventRecord(join[i], b[i]) == hipSuccess) (void)hipStreamWaitEvent(s, join[i], 0);
     hipGraph_t g = nullptr;
     const hipError_t ec = capturing ? hipStreamEndCapture(s, &g) : hipSuccess;
-    if (join) (void)hipEventDestroy(join);
+    for (int i = 0; i < NB; ++i) {
+        if (join[i]) (void)hipEventDestroy(join[i]);
+        if (b[i]) (void)hipStreamDestroy(b[i]);
+    }
     if (fork) (void)hipEventDestroy(fork);
-    if (s2) (void)hipStreamDestroy(s2);
     if (s) (void)hipStreamDestroy(s);
     if (st == PCT_OK && ec != hipSuccess) st = PCT_EHIP;
     if (st != PCT_OK) {
