@@ -28,7 +28,7 @@
 namespace pct {
 
 constexpr int TILE = 256;            // rows per tile (= threads per block of k_count/k_emit)
-constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_THREADS = 1024, SCAN_ITEMS = 4;
 
 // Workspace layout (bytes): [0,256) header | job table | tile sums | tile offsets | counts |
 // per-row path descriptions
@@ -248,27 +248,48 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_tiles(const JobDev *__res
                                                              int64_t T, const int64_t *__restrict__ sums,
                                                              int64_t *__restrict__ offs,
                                                              int64_t *__restrict__ nnz_total) {
+    // chunks of SCAN_THREADS * SCAN_ITEMS sums, loaded and stored coalesced through LDS;
+    // thread t scans items [SCAN_ITEMS t, SCAN_ITEMS (t + 1)) of a chunk, the threads'
+    // totals are scanned across the block (Hillis-Steele), and a carry runs over the chunks
+    __shared__ int64_t buf[SCAN_THREADS * SCAN_ITEMS];
     __shared__ int64_t part[SCAN_THREADS];
-    const int64_t per = (T + SCAN_THREADS - 1) / SCAN_THREADS;
-    const int64_t b0 = (int64_t)threadIdx.x * per;
-    const int64_t b1 = (b0 + per < T) ? b0 + per : T;
-    int64_t acc = 0;
-    for (int64_t t = b0; t < b1; ++t) acc += sums[t];
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the partials
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-        const int64_t v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+    const int t = threadIdx.x;
+    int64_t carry = 0;
+    for (int64_t base = 0; base < T; base += SCAN_THREADS * SCAN_ITEMS) {
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            const int64_t e = base + i * SCAN_THREADS + t;
+            buf[i * SCAN_THREADS + t] = e < T ? sums[e] : 0;
+        }
         __syncthreads();
-        part[threadIdx.x] += v;
+        int64_t acc = 0;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) acc += buf[t * SCAN_ITEMS + i];
+        part[t] = acc;
+        __syncthreads();
+        for (int off = 1; off < SCAN_THREADS; off <<= 1) {
+            const int64_t v = (t >= off) ? part[t - off] : 0;
+            __syncthreads();
+            part[t] += v;
+            __syncthreads();
+        }
+        int64_t run = carry + part[t] - acc;
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            const int64_t v = buf[t * SCAN_ITEMS + i];
+            buf[t * SCAN_ITEMS + i] = run;
+            run += v;
+        }
+        carry += part[SCAN_THREADS - 1];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SCAN_ITEMS; ++i) {
+            const int64_t e = base + i * SCAN_THREADS + t;
+            if (e < T) offs[e] = buf[i * SCAN_THREADS + t];
+        }
         __syncthreads();
     }
-    int64_t run = part[threadIdx.x] - acc;
-    for (int64_t t = b0; t < b1; ++t) {
-        offs[t] = run;
-        run += sums[t];
-    }
-    if (threadIdx.x == SCAN_THREADS - 1) offs[T] = part[SCAN_THREADS - 1];
+    if (t == 0) offs[T] = carry;
     __threadfence_block();
     __syncthreads();
     for (int j = threadIdx.x; j < n_jobs; j += SCAN_THREADS) {
@@ -284,11 +305,24 @@ __global__ void __launch_bounds__(TILE) k_row_ptr(const JobDev *__restrict__ job
                                                   int n_jobs, const int32_t *__restrict__ counts,
                                                   const int64_t *__restrict__ offs) {
     __shared__ int64_t sc[TILE];
+    __shared__ int wsum[TILE / WAVE];
     const int64_t tile = blockIdx.x;
     const int jid = job_of_tile(jobs, corder, n_jobs, tile);
     const JobDev &J = jobs[jid];
     const int64_t r = (tile - J.tile_base) * TILE + threadIdx.x;
     const int64_t c = (r < J.row_count) ? counts[J.count_off + r] : 0;
+    const int64_t base = offs[tile] - offs[J.tile_base];
+    if (offs[tile + 1] - offs[tile] <= INT32_MAX) {
+        // the tile's entries fit in 32 bits: scans per wave (DPP) and over the 4 waves
+        const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+        const int incl = wave_incl_scan((int)c);
+        if (lane == WAVE - 1) wsum[w] = incl;
+        __syncthreads();
+        int before = 0;
+        for (int i = 0; i < w; ++i) before += wsum[i];
+        if (r < J.row_count) J.row_ptr[r] = base + (int64_t)(before + incl - (int)c);
+        return;
+    }
     sc[threadIdx.x] = c;
     __syncthreads();
     for (int off = 1; off < TILE; off <<= 1) {
@@ -297,7 +331,7 @@ __global__ void __launch_bounds__(TILE) k_row_ptr(const JobDev *__restrict__ job
         sc[threadIdx.x] += v;
         __syncthreads();
     }
-    if (r < J.row_count) J.row_ptr[r] = offs[tile] - offs[J.tile_base] + sc[threadIdx.x] - c;
+    if (r < J.row_count) J.row_ptr[r] = base + sc[threadIdx.x] - c;
 }
 
 // Wave-cooperative emit: each wavefront of the block takes 64 rows of the tile.
