@@ -105,6 +105,28 @@ def test_phantom_area_rule_and_turned_regions_bit_exact(P, oracle, W):
         assert np.array_equal(x, xo), (ph["voxelize"], int((x != xo).sum()))
 
 
+def test_corner_rule_runs_bit_exact(P, oracle, W):
+    """The corner rule takes its voxels in runs of four along the last axis, sharing the
+    scaled coordinates of the grid lines between them: grids whose last axis is not a
+    multiple of four (runs of 1 to 3 at the end), a last axis of one voxel, turned and
+    unturned regions, a cylinder among ellipsoids, and c3 jobs of both dimensions, against
+    the oracle bit for bit."""
+    regs2 = W.neo1_regions()
+    regs2[2]["angle_deg"] = 35.0
+    regs3 = W.neo_ellipsoid_regions()
+    regs3.append(W._e((10, -20, 0), (25, 8), 1.2, "ellipse"))   # a cylinder along z
+    regs3.append(W._e((-30, 15, 5), (12, 20, 9), 0.9, "ellipsoid", angle_deg=-50.0))
+    phs = [W.phantom(2, (37, 53), (5.1, 3.7), regs2), W.phantom(2, (29, 1), (6.0, 9.0), regs2),
+           W.phantom(2, (64, 6), (3.0, 30.0), regs2)]
+    for n in ((21, 19, 23), (9, 6, 5), (17, 13, 1), (12, 10, 2), (8, 8, 7)):
+        phs.append(W.phantom(3, n, (200.0 / n[0], 180.0 / n[1], 160.0 / n[2]), regs3))
+    phs += [c["phantom"] for c in W.c3_jobs()[:4]]
+    for ph in phs:
+        x = P.phantom_build(ph).cpu().numpy()
+        xo = oracle.phantom_build(ph)
+        assert np.array_equal(x, xo), (ph["n"], int((x != xo).sum()))
+
+
 def test_turned_outer_boundary_parity(P, oracle, W):
     cfg = W.c_paper_area()
     _compare(P, oracle, cfg, _sample(cfg["beam"]["n_protons"], 3000, 13))
