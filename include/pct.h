@@ -168,8 +168,9 @@ pct_status pct_phantom_build(const pct_phantom *phantom, float *x_dev, void *str
 /* Bytes of device workspace that pct_count_rows / pct_emit_csr / pct_wepl need for
  * these jobs (0 if a descriptor is invalid).  The workspace holds the job table, the
  * per-row counts, the scan partials, a description of every row's path, a status word
- * and, for each 3D job with n[0] <= 1024 and n[1], n[2] <= 2048, a copy of x in bricks
- * of 8 x 8 x 1 voxels that pct_emit_csr and pct_wepl refill from x_dev on every call
+ * and, for each 3D job, and each 2D job with PCT_STRAIGHT paths, with n[0] <= 1024 and
+ * n[1], n[2] <= 2048, a copy of x in bricks of 8 x 8 x 1 voxels that pct_emit_csr and
+ * pct_wepl refill from x_dev on every call
  * (the gathers of b read it: a cache line then covers a patch of a plane instead of a
  * stretch of one grid row).  pct_emit_csr reads the path descriptions that
  * pct_count_rows wrote: pass it the same workspace and the same jobs (output pointers

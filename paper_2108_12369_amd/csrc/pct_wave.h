@@ -689,10 +689,9 @@ struct RowOut {
             else flush_t<false, false, PACK>(n, lane);
         }
     }
-    // MAYPACK: a 3D emit, whose rows may hold packed coordinates
-    template <bool MAYPACK>
+    // rows of a job with a bricked copy of x hold packed coordinates
     __device__ __forceinline__ void flush(int n, int lane) {
-        if (MAYPACK && pack) flush_p<true>(n, lane);
+        if (pack) flush_p<true>(n, lane);
         else flush_p<false>(n, lane);
     }
 };
@@ -874,13 +873,13 @@ __device__ __forceinline__ int32_t col_at(const int32_t stride[3], const int I[3
     return DIM == 3 ? I[0] + stride[1] * I[1] + stride[2] * I[2] : I[0] + stride[1] * I[1];
 }
 
-// What a staged entry holds for its voxel: the column, or for a 3D job with a bricked
-// copy of x its packed coordinates (x in bits 0-9, y in bits 10-20, z in bits 21-31),
+// What a staged entry holds for its voxel: the column, or for a job with a bricked copy
+// of x its packed coordinates (x in bits 0-9, y in bits 10-20, z in bits 21-31),
 // which the copy-out turns into the column and the brick address.  Both are sums of the
 // per-axis steps below, so the walks that stage entries use them unchanged.
 template <int DIM>
 __device__ __forceinline__ void stage_strides(const JobDev &J, int32_t stride[3]) {
-    const bool pack = DIM == 3 && J.xb != nullptr;
+    const bool pack = J.xb != nullptr;
     stride[0] = 1;
     stride[1] = pack ? (1 << PACK_Y) : J.n[0];
     stride[2] = pack ? (1 << PACK_Z) : J.n[0] * J.n[1];
@@ -1377,7 +1376,7 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
         if (!valid && lane == 0) set_status_dev(status, PCT_EINTERNAL);   // not a description of the count pass
         const bool mine = valid && kind != 3;   // kind 3: walked by the per-lane kernel
         out.x = gptr(J.x);
-        out.pack = DIM == 3 && J.xb != nullptr;
+        out.pack = J.xb != nullptr;
         out.xb = gptr((const float *)J.xb);
         out.gn[0] = (uint32_t)J.n[0];
         out.gn[1] = (uint32_t)J.n[1];
@@ -1431,11 +1430,11 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
         if (ne <= STAGE_ROW_MAX) {
             out.commit(lane);
             if (ne > 0) {
-                out.template flush<DIM == 3>((int)ne, lane);
+                out.flush((int)ne, lane);
                 out.fold();
             }
         } else {
-            out.template flush<DIM == 3>((int)min(ne, (int64_t)(STAGE_CAP + 1)), lane);
+            out.flush((int)min(ne, (int64_t)(STAGE_CAP + 1)), lane);
             out.fold();
             out.commit(lane);
         }
