@@ -630,6 +630,10 @@ struct RowOut {
         const int m = store ? (n < len ? n : len) : 0;   // entries stored
         const bool cst = chord > 0.f;
         __builtin_amdgcn_wave_barrier();
+        // the wave's output phase runs at a raised issue priority, back to 0 once the row's
+        // b is stored (emit_rows_wave): its loads and stores go out while the other waves
+        // of the SIMD walk their rows (c3 step 44.2 -> 43.6 ms, same outputs)
+        __builtin_amdgcn_s_setprio(2);
         for (int g0 = 0; g0 < n; g0 += G * WAVE) {
             uint2 v[G];
             float xv[G];
@@ -1446,6 +1450,7 @@ __device__ __forceinline__ void emit_rows_wave(const JobDev &J, char *rowbuf, in
                 if (lane == 0) *gptr(J.b + r) = (float)(bs * (TW)bfac);
             }
         }
+        __builtin_amdgcn_s_setprio(0);   // raised by the row's flush
     }
     if (__builtin_amdgcn_ballot_w64(bad) != 0 && lane == 0) set_status_dev(status, PCT_EINTERNAL);
 }
