@@ -632,7 +632,7 @@ struct RowOut {
         __builtin_amdgcn_wave_barrier();
         // the wave's output phase runs at a raised issue priority, back to 0 once the row's
         // b is stored (emit_rows_wave): its loads and stores go out while the other waves
-        // of the SIMD walk their rows (c3 step 44.2 -> 43.6 ms, same outputs)
+        // of the SIMD walk their rows (the 64-job batch: step 44.2 -> 43.6 ms, same outputs)
         __builtin_amdgcn_s_setprio(2);
         for (int g0 = 0; g0 < n; g0 += G * WAVE) {
             uint2 v[G];
